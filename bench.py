@@ -1,0 +1,273 @@
+"""Benchmark: matrix-free H.v GB/s (fraction of HBM peak) and time to the Lanczos
+ground-state energy, FP32-mixed vs FP64, on one MI355X.
+
+A timed step is one FP32 H.v over the N_s = 15 three-orbital impurity sector
+(3 orbitals + 12 bath levels, N_up = N_dn = 7, D = 6435^2 = 41,409,225) with x
+and y resident in HBM.  value = algorithmic bytes (read x + write y = 8 D) per
+step / step time.  Besides the JSON fields of the common contract the line
+carries: roofline (dominant kernel = the apply), cpu_baseline (the FP64 oracle
+on the host cores, matrix-free literal rows on a bounded sample), fp64 H.v,
+FP32 H.v at N_s = 18 (D = 48620^2), and time-to-E0 for both precisions from
+the same start vector with the same residual target.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-e0] [--no-cpu]
+                       [--no-ns18] [--e0-ns18]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("apply.hip", "ed_internal.h", "tables.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1004_3354_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload):
+    """HBM bytes per launch measured by rocprofv3 counters for this exact kernel
+    source (profiles/apply_traffic.json), else None."""
+    p = os.path.join(ROOT, "profiles", "apply_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except ValueError:
+        return None
+    e = d.get(workload)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def timed_applies(H, x, y, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        H.apply(x, y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        H.apply(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / 1000.0
+
+
+def setup(cfg, prec, jprime=True):
+    from paper_1004_3354_amd import ed, models, workloads as wl
+    phys, sectors = wl.config(cfg, jprime=jprime)
+    nup, ndn = sectors[0]
+    t0 = time.perf_counter()
+    b = ed.Basis(phys["Ns"], nup, ndn)
+    H = ed.Hamiltonian(models.params_from_model(phys), b, prec)
+    import torch
+    torch.cuda.synchronize()
+    return phys, (nup, ndn), b, H, time.perf_counter() - t0
+
+
+def cpu_baseline(cfg, target_s=12.0):
+    """FP64 oracle on the host: literal operator-string rows of the same sector
+    evaluated without storing H, on a random sample of rows."""
+    import numpy as np
+    import oracle as orc
+    from paper_1004_3354_amd import workloads as wl
+    phys, sectors = wl.config(cfg)
+    sec = orc.sector_for(phys, *sectors[0])
+    x = wl.uniform_vector(wl.start_vector_seed(cfg), sec.D)
+    rng = np.random.default_rng(1)
+    n = 20000
+    rows = np.sort(rng.choice(sec.D, n, replace=False))
+    t0 = time.perf_counter()
+    sec.rows_apply(rows, x)
+    dt = time.perf_counter() - t0
+    n = int(min(sec.D, max(n, n * target_s / max(dt, 1e-6))))
+    rows = np.sort(rng.choice(sec.D, n, replace=False))
+    t0 = time.perf_counter()
+    sec.rows_apply(rows, x)
+    dt = time.perf_counter() - t0
+    threads = None
+    try:
+        import ctypes
+        threads = ctypes.CDLL("libgomp.so.1").omp_get_max_threads()
+    except OSError:
+        threads = len(os.sched_getaffinity(0))
+    rate = n / dt                       # rows (output elements) per second
+    return {"value": round(16.0 * rate / 1e9, 4), "unit": "GB/s (FP64 algorithmic: 16 B per output element)",
+            "cores": int(threads), "kind": "oracle",
+            "sample": "%d random rows of the N_s=15 sector, literal Jordan-Wigner operator strings per row "
+                      "(matrix-free oracle path), %.1f s" % (n, dt),
+            "rows_per_s": round(rate, 1)}
+
+
+def time_to_e0(cfg, precs, max_basis, tol, seed_idx):
+    import torch
+    from paper_1004_3354_amd import ed, workloads as wl
+    out = {}
+    v64 = None
+    for prec in precs:
+        phys, nn, b, H, tset = setup(cfg, prec)
+        if v64 is None:
+            v64 = torch.empty(b.D, dtype=torch.float64, device="cuda")
+            ed.fill_random(v64, wl.start_vector_seed(seed_idx), 1)
+        v0 = v64 if prec == ed.ED_FP64 else v64.float()
+        opts = ed.options(tol=tol, max_basis=max_basis)
+        ws = torch.empty(H.workspace_bytes(opts, 1), dtype=torch.uint8, device="cuda")
+        x = torch.empty(b.D, dtype=v0.dtype, device="cuda")
+        H.apply(v0, x)                 # tunes the apply schedule outside the timed region
+        del x
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E, info = H.lanczos_ground(v0, opts, ws=ws, allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = "fp64" if prec == ed.ED_FP64 else "fp32_mixed"
+        out[key] = {"seconds": round(dt, 4), "E0": E, "iters": info["iters"], "restarts": info["restarts"],
+                    "converged": info["converged"], "residual": info["residual"], "setup_s": round(tset, 3)}
+        log("time-to-E0 %s: %.3f s E0=%.12f iters=%d" % (key, dt, E, info["iters"]))
+        del ws, H, b
+        if prec != ed.ED_FP64:
+            del v0
+        torch.cuda.empty_cache()
+    del v64
+    torch.cuda.empty_cache()
+    out["max_basis"] = max_basis
+    out["tol"] = tol
+    if "fp64" in out and "fp32_mixed" in out:
+        e64 = out["fp64"]["E0"]
+        out["fp32_vs_fp64_rel"] = abs(out["fp32_mixed"]["E0"] - e64) / max(1.0, abs(e64))
+        out["speedup_fp32_mixed"] = round(out["fp64"]["seconds"] / out["fp32_mixed"]["seconds"], 3)
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_e0.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))["entries"].get("cfg%d" % cfg)
+        if g:
+            ref = list(g["sectors"].values())[0]["evals"][0]
+            out["oracle_E0"] = ref
+            for k in ("fp64", "fp32_mixed"):
+                if k in out:
+                    out[k]["rel_err_vs_oracle"] = abs(out[k]["E0"] - ref) / max(1.0, abs(ref))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-e0", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ns18", action="store_true")
+    ap.add_argument("--e0-ns18", action="store_true", help="also time-to-E0 at N_s=18 (minutes)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the sector is held by a single MI355X and no multi-GPU "
+              "path is built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1004_3354_amd import ed
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    # ---- headline: FP32 H.v on the N_s = 15 sector
+    phys, nn, b, H, tset = setup(2, ed.ED_FP32)
+    D = b.D
+    x = torch.empty(D, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    ed.fill_random(x, 12345, 0)
+    log("N_s=15 FP32: D=%d setup %.3f s" % (D, tset))
+    wall, evt = timed_applies(H, x, y, args.steps, args.warmup)
+    variant = ed.variant_name(H.current_variant())
+    ms = wall / args.steps * 1e3
+    alg_bytes = 8.0 * D
+    value = alg_bytes * args.steps / wall / 1e9
+    kern_s = evt / args.steps
+    achieved = alg_bytes / kern_s / 1e9
+    log("FP32 H.v: %.4f ms/step (events %.4f ms), %.1f GB/s, schedule %s" % (ms, kern_s * 1e3, value, variant))
+    wl15 = "kanamori_Ns15_3orb_12bath_sector7_7"
+    traffic = traffic_from_profile(wl15)
+    del x, y, H, b
+    torch.cuda.empty_cache()
+
+    # ---- FP64 H.v on the same sector
+    _, _, b64, H64, _ = setup(2, ed.ED_FP64)
+    x = torch.empty(D, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    ed.fill_random(x, 12345, 0)
+    w64, e64 = timed_applies(H64, x, y, max(5, args.steps // 2), 2)
+    fp64 = {"ms_per_apply": round(e64 / max(5, args.steps // 2) * 1e3, 4),
+            "gbps": round(16.0 * D * max(5, args.steps // 2) / e64 / 1e9, 1),
+            "schedule": ed.variant_name(H64.current_variant())}
+    fp64["frac"] = round(fp64["gbps"] / HBM_PEAK_GBS, 4)
+    del x, y, H64, b64
+    torch.cuda.empty_cache()
+
+    # ---- FP32 H.v on the N_s = 18 sector
+    ns18 = None
+    if not args.no_ns18:
+        free, _ = torch.cuda.mem_get_info()
+        if free > 24e9:
+            _, _, b18, H18, t18 = setup(4, ed.ED_FP32)
+            x = torch.empty(b18.D, dtype=torch.float32, device="cuda")
+            y = torch.empty_like(x)
+            ed.fill_random(x, 12345, 0)
+            k18 = max(3, args.steps // 5)
+            w18, e18 = timed_applies(H18, x, y, k18, 2)
+            g18 = 8.0 * b18.D * k18 / e18 / 1e9
+            ns18 = {"workload": "kanamori_Ns18_3orb_15bath_sector9_9", "D": b18.D,
+                    "ms_per_apply": round(e18 / k18 * 1e3, 4), "gbps": round(g18, 1),
+                    "frac": round(g18 / HBM_PEAK_GBS, 4), "setup_s": round(t18, 3),
+                    "schedule": ed.variant_name(H18.current_variant())}
+            log("N_s=18 FP32 H.v: %.3f ms, %.1f GB/s" % (e18 / k18 * 1e3, g18))
+            del x, y, H18, b18
+            torch.cuda.empty_cache()
+
+    # ---- time to E0, FP32-mixed vs FP64, same start vector and target
+    e0 = None
+    if not args.no_e0:
+        e0 = time_to_e0(2, [ed.ED_FP32, ed.ED_FP64], max_basis=100, tol=1e-7, seed_idx=2)
+    e0_18 = None
+    if args.e0_ns18:
+        e0_18 = time_to_e0(4, [ed.ED_FP32, ed.ED_FP64], max_basis=20, tol=1e-7, seed_idx=4)
+
+    cpu = None if args.no_cpu else cpu_baseline(2)
+    if cpu:
+        log("cpu baseline: %s" % cpu)
+
+    rec = {
+        "metric": "H.v HBM GB/s (% peak) + s to Lanczos E0 at N_s=15/18, FP32-mixed vs FP64",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32", "data": "synthetic (seeded baths and SplitMix64 vectors)",
+        "config": {"workload": wl15, "Ns": 15, "sector": list(nn), "D": D,
+                   "step": "one FP32 matrix-free H.v (x, y resident in HBM)", "schedule": variant},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_apply<float,float> (%s)" % variant,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "avg_launch_ms": round(kern_s * 1e3, 5)},
+        "cpu_baseline": cpu,
+        "fp64_hv": fp64,
+        "ns18_hv_fp32": ns18,
+        "time_to_e0_ns15": e0,
+        "time_to_e0_ns18": e0_18,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

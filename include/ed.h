@@ -1,0 +1,254 @@
+/*
+ * ed.h -- C interface of the MI355X exact-diagonalization hot path.
+ *
+ * The library solves the eigenvalue problem the paper states for the impurity
+ * Hamiltonian (Section 2, after Eq. 3: only the lowest eigenstates are needed)
+ * by the iterative scheme of Section 3 (repeated multiplication of H by a trial
+ * vector inside a Lanczos / Arnoldi iteration), one fixed (N_up, N_dn) sector at
+ * a time, with the whole sector held by one GPU.  H is never stored: its
+ * elements are evaluated when needed, the alternative the paper proposes at the
+ * end of Section 3.2.
+ *
+ * Conventions
+ *  - Ns <= 32 sites.  Spin-up site i is fermion mode i, spin-down site i is mode
+ *    Ns+i (all up modes precede all down modes in the Jordan-Wigner order).
+ *  - A one-spin basis state is an Ns-bit string with N_sigma bits set.  Its rank
+ *    is its position in ascending numeric order (combinatorial number system).
+ *  - A sector vector has D = D_up * D_dn elements; element (r_up, r_dn) is at
+ *    flat index r_up * D_dn + r_dn (the down index is contiguous).
+ *  - Vector element type is set per Hamiltonian: ED_FP64 (double) or ED_FP32
+ *    (float storage and arithmetic in H.v; every Lanczos reduction, the
+ *    tridiagonal eigenproblem and the final Rayleigh quotient are FP64).
+ *
+ * Ownership: handles are created and freed by the library.  Every vector and
+ * workspace pointer is device memory owned by the caller (e.g. a torch tensor's
+ * data pointer); small outputs (dimensions, eigenvalues, info) are host memory.
+ * `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *
+ * Errors: every call returns an ed_status; nothing is thrown across this
+ * interface.  The message of the last failure on the calling thread is returned
+ * by ed_last_error().  ED_EINVAL: bad argument (detailed below per call);
+ * ED_ENOMEM: tables or workspace do not fit; ED_EDEVICE: a HIP runtime error;
+ * ED_ENOCONV: iteration limit reached (best estimates are still written);
+ * ED_EUNSUPPORTED: a valid model this build has no kernel for.
+ */
+#ifndef ED_H
+#define ED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ED_OK = 0,
+    ED_EINVAL = 1,
+    ED_ENOMEM = 2,
+    ED_EDEVICE = 3,
+    ED_ENOCONV = 4,
+    ED_EUNSUPPORTED = 5
+} ed_status;
+
+enum { ED_FP64 = 0, ED_FP32 = 1 };
+enum { ED_SPIN_UP = 0, ED_SPIN_DN = 1 };
+/* Four-fermion impurity terms of the multi-orbital Hamiltonian (Section 4). */
+enum { ED_SPIN_FLIP = 1, ED_PAIR_HOP = 2 };
+
+typedef struct ed_basis_s *ed_basis_t;
+typedef struct ed_ham_s *ed_ham_t;
+
+/* Version string of the library build. */
+const char *ed_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *ed_last_error(void);
+
+/* ------------------------------------------------------------ sector basis --
+ * ed_basis: the (N_up, N_dn) sector of an Ns-site model, the block structure
+ * behind every dimension the paper quotes (Introduction; Table 1).  The two
+ * one-spin bases are generated on the current GPU by combinatorial unranking.
+ * EINVAL: Ns outside [1, 32], Nup or Ndn outside [0, Ns], out NULL.
+ * ENOMEM: D_up or D_dn above 2^31 - 1. */
+ed_status ed_basis(int Ns, int Nup, int Ndn, ed_basis_t *out);
+
+/* Dimensions D_up = C(Ns, Nup), D_dn = C(Ns, Ndn), D = D_up * D_dn.
+ * Any output pointer may be NULL. */
+ed_status ed_basis_dims(ed_basis_t b, int64_t *Dup, int64_t *Ddn, int64_t *D);
+
+/* Copy one spin's states (ascending, i.e. in rank order) to HOST memory
+ * host_out[D_sigma].  EINVAL: spin not 0/1 or host_out NULL. */
+ed_status ed_basis_states(ed_basis_t b, int spin, uint32_t *host_out);
+
+/* Rank n bit strings (DEVICE arrays): ranks[i] = position of states[i] in the
+ * spin's ascending basis, or -1 if its popcount is not N_sigma or it has bits
+ * at or above Ns.  Asynchronous on stream. */
+ed_status ed_basis_rank(ed_basis_t b, int spin, const uint32_t *states, int64_t n,
+                        int64_t *ranks, void *stream);
+
+void ed_basis_free(ed_basis_t b);
+
+/* ----------------------------------------------------------- Hamiltonian ----
+ * The operator whose matrix-vector product is the hot loop (Section 3.1,
+ * Listing 1), given by coefficient arrays that cover Eq. (1) (Hubbard), Eq. (2)
+ * (Anderson impurity) and the multi-orbital impurity Hamiltonian of Section 4:
+ *
+ *   H = sum_{s,i} eps[s*Ns+i] n_is
+ *     + sum_{s, i != j} hop[(s*Ns+i)*Ns+j] c+_is c_js
+ *     + sum_{i,j} w_ud[i*Ns+j] n_i,up n_j,dn
+ *     + sum_{s, i<j} w_ss[(s*Ns+i)*Ns+j] n_is n_js
+ *     + sum_t x[t].coef * X_t
+ *
+ * with X_t the spin-flip string  d+_{m up} d_{m dn} d+_{m' dn} d_{m' up}  or the
+ * pair-hopping string  d+_{m up} d+_{m dn} d_{m' up} d_{m' dn}, written exactly
+ * as in the paper (so the Kanamori term -J'[...] has coef = -J').
+ * Requirements (else EINVAL): every value finite; hop[s] symmetric with a zero
+ * diagonal (on-site energies belong in eps); w_ss zero on and below the
+ * diagonal; for x: m != m', both < Ns, type ED_SPIN_FLIP or ED_PAIR_HOP, and the
+ * list Hermitian (the summed coefficient of (type, m, m') equals that of
+ * (type, m', m)).  Off-diagonal w_ud entries may touch at most 8 sites
+ * (else EUNSUPPORTED).  Input arrays are read during the call only.
+ */
+typedef struct {
+    int32_t type;   /* ED_SPIN_FLIP or ED_PAIR_HOP */
+    int32_t m;
+    int32_t mp;
+    double coef;
+} ed_xterm;
+
+typedef struct {
+    int32_t Ns;
+    const double *eps;    /* [2*Ns]        */
+    const double *hop;    /* [2*Ns*Ns]     */
+    const double *w_ud;   /* [Ns*Ns]       */
+    const double *w_ss;   /* [2*Ns*Ns]     */
+    int32_t n_x;
+    const ed_xterm *x;    /* [n_x], may be NULL when n_x == 0 */
+} ed_params;
+
+/* Build the per-spin tables of H for sector b on the current GPU (the paper's
+ * "setup" phase, T_setup in Table 1, in matrix-free form).  precision is ED_FP64
+ * or ED_FP32.  The handle keeps its own copy of the basis dimensions; b may be
+ * freed afterwards. */
+ed_status ed_ham_create(const ed_params *p, ed_basis_t b, int precision, ed_ham_t *out);
+
+ed_status ed_ham_dims(ed_ham_t h, int64_t *Dup, int64_t *Ddn, int64_t *D);
+
+/* Number of entries of one spin's hop table. */
+ed_status ed_hop_table_size(ed_ham_t h, int spin, int64_t *nnz);
+
+/* Export one spin's hop table to HOST arrays, CSR over source ranks:
+ * off[D_sigma+1]; entries off[r]..off[r+1]-1 hold the target rank, the fermion
+ * sign (+1/-1) and the amplitude h_ij of  h_ij c+_i c_j |r>, in ascending target
+ * order.  Any of tgt/sign/amp may be NULL. */
+ed_status ed_hop_table(ed_ham_t h, int spin, int64_t *off, int32_t *tgt, int8_t *sign,
+                       double *amp);
+
+/* y = H x (overwrite) for DEVICE vectors of D elements of the handle's
+ * precision.  Asynchronous on stream.  EINVAL: NULL pointers or x == y. */
+ed_status ed_apply_H(ed_ham_t h, const void *x, void *y, void *stream);
+
+/* Schedule control.  The apply has several compiled schedules (rows per
+ * workgroup, workgroup size, LDS staging of rows); the first ed_apply_H call on a
+ * handle times every one that fits on the caller's x and y (synchronously) and
+ * keeps the fastest (the environment variable ED_APPLY_VARIANT=<n> forces one).
+ * These calls run or query a given schedule, e.g. to test each against a
+ * reference.  ed_apply_H_variant returns EINVAL for a schedule that does not fit. */
+int ed_apply_variant_count(void);
+const char *ed_apply_variant_name(int variant);
+int ed_apply_variant_fits(ed_ham_t h, int variant);
+int ed_apply_current_variant(ed_ham_t h);
+ed_status ed_apply_H_variant(ed_ham_t h, int variant, const void *x, void *y, void *stream);
+
+/* FP64-accurate Rayleigh quotient and residual of a DEVICE vector x stored in
+ * the handle's precision: rq = <x,Hx>/<x,x>, resid = ||Hx - rq x|| / ||x||, with
+ * H x evaluated in FP64 arithmetic and never stored.  Synchronous. */
+ed_status ed_rayleigh(ed_ham_t h, const void *x, double *rq, double *resid, void *stream);
+
+/* Fill a DEVICE vector with n numbers of the counter-based SplitMix64 stream
+ * `seed` (element i uses output i, or outputs 2i and 2i+1): dist 0 = uniform on
+ * [-1, 1), dist 1 = standard normal (Box-Muller).  precision ED_FP64 or ED_FP32
+ * (the FP32 value is the round-to-nearest cast of the FP64 one). */
+ed_status ed_fill_random(void *x, int64_t n, uint64_t seed, int dist, int precision,
+                         void *stream);
+
+void ed_ham_free(ed_ham_t h);
+
+/* ------------------------------------------------------------ eigensolvers --
+ * Lanczos iteration (Section 3) with full reorthogonalisation against every
+ * stored basis vector, FP64 reductions, a tridiagonal eigensolve on the GPU and
+ * restarts when the stored basis is full. */
+typedef struct {
+    int32_t max_iter;     /* total Lanczos steps over all restarts (default 600)    */
+    int32_t max_basis;    /* stored basis vectors before a restart (default 120)    */
+    double tol;           /* stop when |beta_j s_j| <= tol * max(|theta|, 1) (1e-10) */
+    int32_t reorth;       /* Gram-Schmidt passes per step: 0, 1 or 2 (default 2)    */
+    int32_t check_every;  /* steps between convergence tests (default 4)            */
+    int32_t refine;       /* 1: report the FP64 Rayleigh quotient of the Ritz vector */
+} ed_lanczos_opts;
+
+typedef struct {
+    int32_t iters;        /* Lanczos steps taken (all restarts)                  */
+    int32_t restarts;
+    int32_t converged;    /* 1 if the residual test was met                     */
+    int32_t basis_used;   /* largest number of stored basis vectors             */
+    double residual;      /* ||H psi - E psi|| / ||psi|| of the returned vector  */
+    double ritz;          /* Ritz value from the tridiagonal matrix             */
+    double rq_fp64;       /* FP64 Rayleigh quotient (equals the reported E)     */
+} ed_info;
+
+/* Fill opts with the defaults above. */
+void ed_lanczos_defaults(ed_lanczos_opts *opts);
+
+/* Bytes of DEVICE workspace ed_lanczos_ground (k = 1) or ed_arnoldi_lowest (k)
+ * needs with these options.  EINVAL: k < 1 or k > D. */
+ed_status ed_workspace_bytes(ed_ham_t h, const ed_lanczos_opts *opts, int k, size_t *bytes);
+
+/* Lowest eigenvalue of the sector.  v0: DEVICE start vector (D elements, any
+ * nonzero norm).  ws: DEVICE workspace of ws_bytes >= ed_workspace_bytes(...,1).
+ * psi0: optional DEVICE output for the normalised ground-state vector.  E0 is
+ * the FP64 Rayleigh quotient of that vector when opts->refine, else the Ritz
+ * value.  Synchronous on stream.  ED_ENOCONV: max_iter reached (E0, psi0 and
+ * info still hold the best estimate).  A Krylov breakdown (exact invariant
+ * subspace) is a success. */
+ed_status ed_lanczos_ground(ed_ham_t h, const ed_lanczos_opts *opts, const void *v0,
+                            void *ws, size_t ws_bytes, double *E0, void *psi0,
+                            ed_info *info, void *stream);
+
+/* The k lowest eigenvalues, counted with multiplicity, ascending, into HOST
+ * evals[k]; optional DEVICE evecs[k][D].  Each eigenpair is found by a restarted
+ * Lanczos run on H restricted to the orthogonal complement of the pairs already
+ * locked (explicit deflation), which also recovers every copy of a degenerate
+ * eigenvalue.  info[k] (HOST, may be NULL) per eigenpair. */
+ed_status ed_arnoldi_lowest(ed_ham_t h, int k, const ed_lanczos_opts *opts, const void *v0,
+                            void *ws, size_t ws_bytes, double *evals, void *evecs,
+                            ed_info *info, void *stream);
+
+/* ------------------------------------------------------- sector batching ----
+ * All sectors of one impurity problem at once (the paper's solver treats the
+ * sectors of the block structure one after another): one restarted Lanczos per
+ * sector, all advanced in lockstep; every step is a fixed sequence of batched
+ * kernels over all sectors whose step index lives in device memory, captured
+ * once in a hipGraph and replayed, with converged sectors masked off on the
+ * device.  The apply runs over row tiles of about T output elements per
+ * workgroup, T picked on the first step by timing candidates
+ * (ED_BATCH_TILE=<T> forces one; ed_batched_last_tile reports the choice).
+ * hs: nsec handles of one precision on one GPU.  v0s: optional HOST array of
+ * nsec DEVICE start vectors (NULL: sector i starts from the SplitMix64 normal
+ * stream seed + i).  E0: HOST [nsec] lowest eigenvalue per sector (FP64
+ * Rayleigh quotient of the Ritz vector when opts->refine).  info: HOST [nsec]
+ * or NULL.  ws: DEVICE workspace of at least ed_batched_workspace_bytes.
+ * Synchronous.  ED_ENOCONV if some sector hit max_iter (all E0 still written). */
+ed_status ed_batched_workspace_bytes(int nsec, const ed_ham_t *hs, const ed_lanczos_opts *opts,
+                                     size_t *bytes);
+ed_status ed_lanczos_ground_batched(int nsec, const ed_ham_t *hs, const ed_lanczos_opts *opts,
+                                    const void *const *v0s, uint64_t seed, void *ws, size_t ws_bytes,
+                                    double *E0, ed_info *info, void *stream);
+int64_t ed_batched_last_tile(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ED_H */

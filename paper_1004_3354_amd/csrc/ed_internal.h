@@ -1,0 +1,229 @@
+// Internal declarations of the HIP exact-diagonalization library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ed.h"
+
+namespace ed {
+
+// ----------------------------------------------------------------- errors --
+struct Failure {
+    ed_status st;
+};
+[[noreturn]] void fail(ed_status st, const char *fmt, ...);
+[[noreturn]] void throw_hip(hipError_t e, const char *what, const char *file, int line);
+void clear_error();
+
+#define ED_HIP(call)                                                   \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) ::ed::throw_hip(e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define ED_LAUNCH_CHECK() ED_HIP(hipGetLastError())
+
+// Runs body, translating internal failures into a status code.
+template <class F>
+ed_status guard(F &&body) {
+    try {
+        clear_error();
+        body();
+        return ED_OK;
+    } catch (const Failure &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        try { fail(ED_ENOMEM, "host allocation failed"); } catch (const Failure &f) { return f.st; }
+    } catch (...) {
+        try { fail(ED_EDEVICE, "unexpected C++ exception"); } catch (const Failure &f) { return f.st; }
+    }
+    return ED_EDEVICE;
+}
+
+// Restores the caller's current device on exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        ED_HIP(hipGetDevice(&prev));
+        if (prev != dev) ED_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Owned device allocation (library-internal tables only; vectors belong to the caller).
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem() { release(); }
+    void alloc(size_t n) {
+        release();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(ED_ENOMEM, "device allocation of %zu bytes failed (%s)", n, hipGetErrorString(e));
+        }
+        bytes = n;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+inline unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// --------------------------------------------------------------- binomials --
+// C(n, k) for 0 <= n, k <= 32 on the host (all fit in 32 bits).
+uint64_t binom_host(int n, int k);
+void ensure_device_binomials();  // uploads the constant table on the current device
+int64_t basis_rank_host(uint32_t s, int ns, int n);
+
+// ------------------------------------------------------------------ basis --
+struct BasisData {
+    int ns = 0, n[2] = {0, 0};
+    int64_t dim[2] = {0, 0};
+    DevMem states[2];
+};
+
+}  // namespace ed
+
+struct ed_basis_s {
+    int device = 0;
+    ed::BasisData b;
+};
+
+namespace ed {
+
+// ------------------------------------------------------------ spin tables --
+// Tables of one spin species.  Arrays suffixed 64/32 hold FP64 / FP32 copies.
+struct SpinTab {
+    int ns = 0, n = 0;
+    int64_t dim = 0, nnz = 0, nslices = 0;
+    int max_hops = 0;
+    DevMem states;            // uint32 [dim]
+    DevMem off;               // int32 [dim+1]   CSR over source ranks
+    DevMem tgt;               // int32 [nnz]     target rank, ascending per row
+    DevMem sgn;               // int8  [nnz]
+    DevMem amp;               // double [nnz]    h_ij (export)
+    DevMem sa64, sa32;        // signed amplitude per entry
+    DevMem ell_off;           // int32 [nslices+1] start (in entries) of each 64-state slice
+    DevMem ell_tgt;           // int32 [ell_off[nslices]]  (slice, hop k, lane) -> target
+    DevMem ell_sa64, ell_sa32;
+    DevMem ediag64, ediag32;  // one-spin diagonal piece: eps n + same-spin density terms
+    DevMem cidx;              // uint8 [dim] bits of the state on the cross-term support
+    int nmv = 0;              // number of move tables
+    DevMem mv;                // int32 [nmv][dim] (target << 1 | sign bit) or -1
+    std::vector<int> mv_src, mv_dst;  // move q: electron src -> dst
+};
+
+// Four-fermion term in factorised form: output (u, d) pulls x[up_mv(u), dn_mv(d)].
+struct XTerm {
+    int32_t up_mv;    // index into the up spin's move tables
+    int32_t dn_mv;    // index into the down spin's move tables
+    double amp;       // element = amp * s_up * s_dn
+};
+
+template <typename TA>
+struct XTermDev {
+    int32_t up_mv, dn_mv;
+    TA amp;
+};
+
+// Apply kernel schedule: one of the compiled variants.
+struct ApplyPlan {
+    int variant = -1;   // index into the variant table; -1 = not tuned yet
+};
+
+}  // namespace ed
+
+struct ed_ham_s {
+    int device = 0;
+    int prec = ED_FP64;
+    int ns = 0, nup = 0, ndn = 0;
+    int64_t dup = 0, ddn = 0, D = 0;
+    ed::SpinTab sp[2];
+    // cross term sum_ij w_ud[i][j] n_i,up n_j,dn
+    int umode = 0;              // 0: no on-site part, 1: uniform U0 on umask, 2: per-site values
+    uint32_t umask = 0;
+    double U0 = 0.0;
+    ed::DevMem usite64, usite32;  // [32]
+    int koff = 0;               // number of sites carrying off-diagonal w_ud entries
+    ed::DevMem xtab64, xtab32;  // [4^koff]
+    // four-fermion terms
+    int nx = 0;
+    std::vector<ed::XTerm> xterms;
+    ed::DevMem xt64, xt32;      // XTermDev<double>/<float> [nx]
+    ed::ApplyPlan plan;
+    ed::DevMem redbuf;          // small FP64 reduction scratch owned by the handle
+    size_t redbuf_doubles = 0;
+};
+
+namespace ed {
+
+// Arguments of the matrix-free apply: everything by pointer, element type TA.
+template <typename TX, typename TA>
+struct ApplyArgs {
+    const TX *x;
+    TX *y;
+    int64_t dup, ddn;
+    // rows (spin up): CSR, read wave-uniformly
+    const int32_t *up_off, *up_tgt;
+    const TA *up_sa, *up_e;
+    const uint32_t *up_st;
+    const uint8_t *up_c;
+    const int32_t *up_mv;
+    // columns (spin down): sliced ELL
+    const int32_t *dn_ell_off, *dn_ell_tgt;
+    const TA *dn_ell_sa, *dn_e;
+    const uint32_t *dn_st;
+    const uint8_t *dn_c;
+    const int32_t *dn_mv;
+    // cross term
+    int umode;
+    uint32_t umask;
+    TA U0;
+    const TA *usite;
+    int koff;
+    const TA *xtab;
+    // four-fermion terms
+    int nx;
+    const XTermDev<TA> *xt;
+    // reductions (Rayleigh quotient / residual epilogues)
+    double *partials;
+    double theta;
+};
+
+// Build all tables of a Hamiltonian handle (tables.hip).
+void build_tables(ed_ham_s *h, const ed_params *p, const BasisData &b);
+
+// Launch the apply (apply.hip). mode: 0 = store y, 1 = RQ partials, 2 = residual partials.
+void apply_launch(ed_ham_s *h, const void *x, void *y, hipStream_t s);
+void apply_launch_variant(ed_ham_s *h, int variant, const void *x, void *y, hipStream_t s);
+int apply_variant_count(const ed_ham_s *h);
+const char *apply_variant_name(const ed_ham_s *h, int variant);
+void rayleigh_fp64(ed_ham_s *h, const void *x, double *rq, double *resid, hipStream_t s);
+
+// Deterministic FP64 reductions (lanczos.hip)
+int reduce_blocks(int64_t n);
+
+}  // namespace ed

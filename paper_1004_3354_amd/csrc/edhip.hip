@@ -1,0 +1,8 @@
+// Single translation unit of the library: the constant binomial table and the
+// device helpers are shared by every kernel without relocatable device code.
+#include "basis.hip"
+#include "tables.hip"
+#include "apply.hip"
+#include "lanczos.hip"
+#include "fill.hip"
+#include "batched.hip"

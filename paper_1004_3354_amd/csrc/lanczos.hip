@@ -1,0 +1,675 @@
+// Lanczos iteration for the lowest eigenpairs (Section 3: an iterative solver
+// built on repeated products of H with a trial vector; for real symmetric H the
+// Arnoldi process of the paper's solver reduces to Lanczos with a tridiagonal
+// projected matrix).
+//
+// Storage: basis vector i is v_i = sigma_i * S_i with S_i stored in the
+// handle's precision and sigma_i an FP64 scale, so a new vector is never
+// rescaled in memory.  One step j:
+//   Y = H S_j                                  (matrix-free apply)
+//   a_i = <S_i, Y> over locked vectors and S_0..S_j, gamma_i = sigma_i^2 a_i
+//   Y <- Y - sum_i gamma_i S_i                 (classical Gram-Schmidt)
+//   repeated once more ("twice is enough"), alpha_j = sum of the two gamma_j
+//   beta_j = sigma_j ||Y||, sigma_{j+1} = 1 / ||Y||, S_{j+1} = Y
+// All dot products and updates accumulate in FP64 with a fixed reduction
+// order, so runs are bit-reproducible.  The lowest eigenpair of the j x j
+// tridiagonal matrix comes from a one-workgroup multisection (Sturm counts) and
+// inverse iteration; convergence is |beta_j s_j| <= tol max(|theta|, 1).
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
+#include "ed_internal.h"
+
+namespace ed {
+
+static constexpr int kRedBS = 256;
+static constexpr int kMaxVec = 1024;  // locked + stored basis vectors per kernel
+
+int reduce_blocks(int64_t n) {
+    int64_t b = (n + 4095) / 4096;
+    if (b < 1) b = 1;
+    if (b > 2048) b = 2048;
+    return (int)b;
+}
+
+// contiguous element range of block `blk` out of `nblk`
+__device__ __forceinline__ void block_range(int64_t n, int nblk, int blk, int64_t &a, int64_t &b) {
+    int64_t chunk = (n + nblk - 1) / nblk;
+    chunk = (chunk + 63) & ~(int64_t)63;
+    a = (int64_t)blk * chunk;
+    b = a + chunk;
+    if (a > n) a = n;
+    if (b > n) b = n;
+}
+
+template <int BS>
+__device__ __forceinline__ double block_sum_any(double v, double *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < BS / 64; ++k) s += red[k];
+    __syncthreads();
+    return s;
+}
+
+// partials[v * nblk + blk] = sum over the block's range of S_v[n] * Y[n]
+template <typename TX, int G>
+__global__ __launch_bounds__(kRedBS) void k_multidot(const TX *const *vecs, int nvec, const TX *y, int64_t n,
+                                                     double *partials) {
+    __shared__ double red[kRedBS / 64];
+    const int nblk = gridDim.x, blk = blockIdx.x;
+    int64_t a, b;
+    block_range(n, nblk, blk, a, b);
+    for (int g0 = 0; g0 < nvec; g0 += G) {
+        double acc[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) acc[i] = 0.0;
+        const TX *vp[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) vp[i] = vecs[(g0 + i < nvec) ? g0 + i : g0];
+        for (int64_t k = a + threadIdx.x; k < b; k += kRedBS) {
+            const double yv = (double)y[k];
+#pragma unroll
+            for (int i = 0; i < G; ++i)
+                if (g0 + i < nvec) acc[i] += (double)vp[i][k] * yv;
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (g0 + i >= nvec) break;
+            const double s = block_sum_any<kRedBS>(acc[i], red);
+            if (threadIdx.x == 0) partials[(int64_t)(g0 + i) * nblk + blk] = s;
+        }
+    }
+}
+
+// Y[n] = post * ((assign ? 0 : Y[n]) - sum_i coef[i] S_i[n]) with post =
+// sqrt(*post_sig2) (1 if NULL); optional norm partials of the stored result.
+template <typename TX>
+__global__ __launch_bounds__(kRedBS) void k_lincomb(const TX *const *vecs, const double *coef, int nvec, TX *y,
+                                                    int64_t n, int assign, double sign, double *norm_part,
+                                                    const double *post_sig2) {
+    __shared__ double c[kMaxVec];
+    __shared__ const TX *p[kMaxVec];
+    __shared__ double red[kRedBS / 64];
+    for (int i = threadIdx.x; i < nvec; i += kRedBS) {
+        c[i] = sign * coef[i];
+        p[i] = vecs[i];
+    }
+    __syncthreads();
+    int64_t a, b;
+    block_range(n, gridDim.x, blockIdx.x, a, b);
+    const double post = post_sig2 ? sqrt(*post_sig2) : 1.0;
+    double nrm = 0.0;
+    for (int64_t k = a + threadIdx.x; k < b; k += kRedBS) {
+        double v = assign ? 0.0 : (double)y[k];
+        for (int i = 0; i < nvec; ++i) v -= c[i] * (double)p[i][k];
+        const TX st = (TX)(post * v);
+        y[k] = st;
+        nrm += (double)st * (double)st;
+    }
+    if (norm_part) {
+        const double s = block_sum_any<kRedBS>(nrm, red);
+        if (threadIdx.x == 0) norm_part[blockIdx.x] = s;
+    }
+}
+
+__global__ void k_scale(void *y, int64_t n, double f, int is_f32) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        if (is_f32) {
+            float *p = (float *)y;
+            p[k] = (float)((double)p[k] * f);
+        } else {
+            double *p = (double *)y;
+            p[k] = p[k] * f;
+        }
+    }
+}
+
+// Fixed-order sum of partials[v*nblk + 0..nblk) for each v; gamma[v] =
+// sig2[v] * sum.  If alpha != NULL, *alpha += gamma[jidx].
+__global__ void k_finalize_dots(const double *partials, int nvec, int nblk, const double *sig2, double *raw,
+                                double *gamma, double *alpha, int jidx) {
+    __shared__ double sh[256];
+    for (int v = 0; v < nvec; ++v) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nblk; i += 256) s += partials[(int64_t)v * nblk + i];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (raw) raw[v] = sh[0];
+            if (gamma) gamma[v] = (sig2 ? sig2[v] : 1.0) * sh[0];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && alpha && gamma) *alpha += gamma[jidx];
+}
+
+// After the last update of step j the stored Y is w'' = sigma_j (Y - ...):
+// n2 = ||w''||^2 -> beta[j] = sqrt(n2), sig2[j+1] = 1/n2 (0 on exact breakdown).
+__global__ void k_finalize_norm(const double *partials, int nblk, double *sig2, double *beta, int jidx, int j) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 256) s += partials[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n2 = sh[0];
+        beta[j] = sqrt(n2);
+        sig2[jidx + 1] = n2 > 0.0 ? 1.0 / n2 : 0.0;
+    }
+}
+
+__device__ int sturm_count(const double *al, const double *be, int m, double x, double pivmin) {
+    int c = 0;
+    double q = al[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++c;
+    for (int i = 1; i < m; ++i) {
+        q = (al[i] - x) - be[i - 1] * be[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) ++c;
+    }
+    return c;
+}
+
+// Lowest eigenpair of the m x m symmetric tridiagonal (alpha, beta) matrix.
+// out[0] = theta, out[1] = |beta_last s_{m-1}|, out[2] = beta_last,
+// out[3 .. 3+m) = normalised eigenvector.  One workgroup of 256 threads.
+__device__ void k_tridiag_lowest_body(const double *alpha, const double *beta, int m, double *out,
+                                      double *work) {
+    __shared__ double al[1024], be[1024];
+    __shared__ int cnt[256];
+    __shared__ double lo, hi;
+    const int t = threadIdx.x;
+    for (int i = t; i < m; i += 256) {
+        al[i] = alpha[i];
+        be[i] = (i < m - 1) ? beta[i] : 0.0;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double l = 1e300, h = -1e300, bmax = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i < m - 1 ? fabs(be[i]) : 0.0);
+            l = fmin(l, al[i] - r);
+            h = fmax(h, al[i] + r);
+            bmax = fmax(bmax, fabs(be[i]));
+        }
+        const double w = 1e-12 * fmax(fmax(fabs(l), fabs(h)), 1.0);
+        lo = l - w;
+        hi = h + w;
+        work[0] = fmax(1e-290, 1e-300 * bmax * bmax);
+    }
+    __syncthreads();
+    const double pivmin = work[0];
+    for (int it = 0; it < 60; ++it) {
+        const double L = lo, H = hi;
+        const double x = L + (H - L) * (double)(t + 1) / 257.0;
+        cnt[t] = sturm_count(al, be, m, x, pivmin);
+        __syncthreads();
+        if (t == 0) {
+            int f = -1;
+            for (int k = 0; k < 256; ++k)
+                if (cnt[k] >= 1) {
+                    f = k;
+                    break;
+                }
+            double nl, nh;
+            if (f < 0) {
+                nl = L + (H - L) * 256.0 / 257.0;
+                nh = H;
+            } else {
+                nh = L + (H - L) * (double)(f + 1) / 257.0;
+                nl = (f > 0) ? L + (H - L) * (double)f / 257.0 : L;
+            }
+            lo = nl;
+            hi = nh;
+        }
+        __syncthreads();
+        if (hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
+    }
+    if (t != 0) return;
+    const double theta = 0.5 * (lo + hi);
+    // inverse iteration with Gaussian elimination and partial pivoting
+    double *d = work + 8, *dl = d + m, *du = dl + m, *du2 = du + m, *z = du2 + m;
+    int *piv = (int *)(z + m);
+    for (int i = 0; i < m; ++i) z[i] = 1.0;
+    for (int rep = 0; rep < 3; ++rep) {
+        for (int i = 0; i < m; ++i) {
+            d[i] = al[i] - theta;
+            dl[i] = (i < m - 1) ? be[i] : 0.0;
+            du[i] = (i < m - 1) ? be[i] : 0.0;
+            du2[i] = 0.0;
+            piv[i] = 0;
+        }
+        const double tiny = 1e-300 + 2.220446049250313e-16 * fmax(fabs(theta), 1.0) * 1e-3;
+        for (int i = 0; i < m - 1; ++i) {
+            if (fabs(d[i]) >= fabs(dl[i])) {
+                if (d[i] == 0.0) d[i] = tiny;
+                const double f = dl[i] / d[i];
+                dl[i] = f;
+                d[i + 1] -= f * du[i];
+                piv[i] = 0;
+            } else {
+                const double f = d[i] / dl[i];
+                d[i] = dl[i];
+                dl[i] = f;
+                const double tmp = du[i];
+                du[i] = d[i + 1];
+                d[i + 1] = tmp - f * d[i + 1];
+                if (i < m - 2) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = -f * du[i + 1];
+                }
+                piv[i] = 1;
+            }
+        }
+        if (d[m - 1] == 0.0) d[m - 1] = tiny;
+        // forward: L
+        for (int i = 0; i < m - 1; ++i) {
+            if (piv[i] == 0) {
+                z[i + 1] -= dl[i] * z[i];
+            } else {
+                const double tmp = z[i];
+                z[i] = z[i + 1];
+                z[i + 1] = tmp - dl[i] * z[i];
+            }
+        }
+        // backward: U (three diagonals)
+        z[m - 1] /= d[m - 1];
+        if (m > 1) z[m - 2] = (z[m - 2] - du[m - 2] * z[m - 1]) / d[m - 2];
+        for (int i = m - 3; i >= 0; --i) z[i] = (z[i] - du[i] * z[i + 1] - du2[i] * z[i + 2]) / d[i];
+        double mx = 0.0;
+        for (int i = 0; i < m; ++i) mx = fmax(mx, fabs(z[i]));
+        if (!(mx > 0.0) || !isfinite(mx)) {
+            for (int i = 0; i < m; ++i) z[i] = 1.0;
+            mx = 1.0;
+        }
+        double nn = 0.0;
+        for (int i = 0; i < m; ++i) {
+            z[i] /= mx;
+            nn += z[i] * z[i];
+        }
+        nn = sqrt(nn);
+        for (int i = 0; i < m; ++i) z[i] /= nn;
+    }
+    if (z[0] < 0.0)
+        for (int i = 0; i < m; ++i) z[i] = -z[i];
+    const double bl = beta[m - 1];
+    out[0] = theta;
+    out[1] = fabs(bl * z[m - 1]);
+    out[2] = bl;
+    for (int i = 0; i < m; ++i) out[3 + i] = z[i];
+}
+
+__global__ __launch_bounds__(256) void k_tridiag_lowest(const double *alpha, const double *beta, int m,
+                                                        double unused, double *out, double *work) {
+    k_tridiag_lowest_body(alpha, beta, m, out, work);
+}
+
+// coef[i] = s_i * sigma_i for the Ritz combination psi = sum_i s_i v_i
+__global__ void k_ritz_coef(const double *s, const double *sig2, int m, double *coef) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) coef[i] = s[i] * sqrt(sig2[i]);
+}
+
+__global__ void k_set_sig2(double *sig2, int idx, const double *raw) {
+    if (threadIdx.x == 0) sig2[idx] = raw[0] > 0.0 ? 1.0 / raw[0] : 0.0;
+}
+
+__global__ void k_zero(double *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
+// ------------------------------------------------------------- workspace --
+struct Carve {
+    char *base;
+    size_t off = 0, cap;
+    void *take(size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        void *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+struct Work {
+    int m = 0, kmax = 0, nblk = 0;
+    size_t elem = 0;
+    std::vector<void *> slots;   // m + 1 basis slots
+    std::vector<void *> locked;  // kmax locked-vector slots (may point into evecs)
+    const void **vp = nullptr;   // device array of vector pointers [kmax + m + 1]
+    double *sig2 = nullptr, *gamma = nullptr, *raw = nullptr, *alpha = nullptr, *beta = nullptr;
+    double *partials = nullptr, *tri = nullptr, *triwork = nullptr, *coef = nullptr;
+};
+
+static void fill_defaults(ed_lanczos_opts &o) {
+    o.max_iter = 600;
+    o.max_basis = 120;
+    o.tol = 1e-10;
+    o.reorth = 2;
+    o.check_every = 4;
+    o.refine = 1;
+}
+
+static ed_lanczos_opts effective(const ed_lanczos_opts *opts, int64_t D) {
+    ed_lanczos_opts o;
+    fill_defaults(o);
+    if (opts) o = *opts;
+    if (o.max_iter <= 0) o.max_iter = 600;
+    if (o.max_basis <= 1) o.max_basis = 120;
+    if (o.max_basis > 1000) o.max_basis = 1000;
+    if ((int64_t)o.max_basis > D) o.max_basis = (int)std::max<int64_t>(D, 1);
+    if (!(o.tol > 0.0)) o.tol = 1e-10;
+    if (o.reorth < 0 || o.reorth > 2) o.reorth = 2;
+    if (o.check_every <= 0) o.check_every = 4;
+    return o;
+}
+
+// Lay out the workspace; with base == nullptr only the size is computed.
+static size_t layout(Work &w, char *base, int64_t D, size_t elem, int m, int kmax, bool locked_in_ws) {
+    Carve c{base, 0, 0};
+    w.m = m;
+    w.kmax = kmax;
+    w.elem = elem;
+    w.nblk = reduce_blocks(D);
+    w.slots.assign(m + 1, nullptr);
+    for (int i = 0; i <= m; ++i) w.slots[i] = c.take((size_t)D * elem);
+    w.locked.assign(kmax, nullptr);
+    if (locked_in_ws)
+        for (int i = 0; i < kmax; ++i) w.locked[i] = c.take((size_t)D * elem);
+    const int nv = kmax + m + 2;
+    w.vp = (const void **)c.take((size_t)nv * sizeof(void *));
+    w.sig2 = (double *)c.take((size_t)nv * sizeof(double));
+    w.gamma = (double *)c.take((size_t)nv * sizeof(double));
+    w.raw = (double *)c.take((size_t)nv * sizeof(double));
+    w.coef = (double *)c.take((size_t)nv * sizeof(double));
+    w.alpha = (double *)c.take((size_t)(m + 2) * sizeof(double));
+    w.beta = (double *)c.take((size_t)(m + 2) * sizeof(double));
+    w.partials = (double *)c.take((size_t)nv * (size_t)w.nblk * sizeof(double));
+    w.tri = (double *)c.take((size_t)(m + 8) * sizeof(double));
+    w.triwork = (double *)c.take((size_t)(8 + 6 * (m + 2)) * sizeof(double) + (size_t)(m + 2) * sizeof(int) + 64);
+    return c.off + 256;
+}
+
+// ----------------------------------------------------------------- solver --
+struct Solver {
+    ed_ham_s *h;
+    hipStream_t s;
+    ed_lanczos_opts o;
+    Work w;
+    int nlock = 0;
+    std::vector<double> lock_sig2;
+
+    template <typename TX>
+    void multidot(int vbeg, int nvec, const void *y) {
+        const TX *const *vecs = (const TX *const *)(w.vp + vbeg);
+        k_multidot<TX, 8><<<w.nblk, kRedBS, 0, s>>>(vecs, nvec, (const TX *)y, h->D, w.partials);
+        ED_LAUNCH_CHECK();
+    }
+    template <typename TX>
+    void lincomb(int vbeg, const double *coef, int nvec, void *y, int assign, double sign, double *normp,
+                 const double *post) {
+        const TX *const *vecs = (const TX *const *)(w.vp + vbeg);
+        k_lincomb<TX><<<w.nblk, kRedBS, 0, s>>>(vecs, coef, nvec, (TX *)y, h->D, assign, sign, normp, post);
+        ED_LAUNCH_CHECK();
+    }
+    void dots(int vbeg, int nvec, const void *y, double *alpha, int jrel) {
+        if (h->prec == ED_FP64) multidot<double>(vbeg, nvec, y);
+        else multidot<float>(vbeg, nvec, y);
+        k_finalize_dots<<<1, 256, 0, s>>>(w.partials, nvec, w.nblk, w.sig2 + vbeg, w.raw, w.gamma + vbeg, alpha, jrel);
+        ED_LAUNCH_CHECK();
+    }
+    void update(int vbeg, int nvec, void *y, double *normp, const double *post = nullptr) {
+        if (h->prec == ED_FP64) lincomb<double>(vbeg, w.gamma + vbeg, nvec, y, 0, 1.0, normp, post);
+        else lincomb<float>(vbeg, w.gamma + vbeg, nvec, y, 0, 1.0, normp, post);
+    }
+    void combine(int vbeg, const double *coef, int nvec, void *out) {  // out = sum coef_i S_i
+        if (h->prec == ED_FP64) lincomb<double>(vbeg, coef, nvec, out, 1, -1.0, nullptr, nullptr);
+        else lincomb<float>(vbeg, coef, nvec, out, 1, -1.0, nullptr, nullptr);
+    }
+    void upload_pointers(const std::vector<void *> &krylov) {
+        std::vector<const void *> v;
+        for (int i = 0; i < nlock; ++i) v.push_back(w.locked[i]);
+        for (void *p : krylov) v.push_back(p);
+        ED_HIP(hipMemcpyAsync(w.vp, v.data(), v.size() * sizeof(void *), hipMemcpyHostToDevice, s));
+        if (nlock)
+            ED_HIP(hipMemcpyAsync(w.sig2, lock_sig2.data(), (size_t)nlock * sizeof(double), hipMemcpyHostToDevice, s));
+        ED_HIP(hipStreamSynchronize(s));
+    }
+    // vector norm^2 of y via a one-vector multidot with pointer slot `idx`
+    double norm2_sync(int idx, const void *y) {
+        if (h->prec == ED_FP64) multidot<double>(idx, 1, y);
+        else multidot<float>(idx, 1, y);
+        k_finalize_dots<<<1, 256, 0, s>>>(w.partials, 1, w.nblk, nullptr, w.raw, nullptr, nullptr, 0);
+        ED_LAUNCH_CHECK();
+        double r = 0.0;
+        ED_HIP(hipMemcpyAsync(&r, w.raw, sizeof(double), hipMemcpyDeviceToHost, s));
+        ED_HIP(hipStreamSynchronize(s));
+        return r;
+    }
+    // orthogonalise the first Krylov slot against the locked vectors (twice),
+    // scale it to unit norm and set sigma_0 from the stored values.
+    double prepare_start(void *s0) {
+        for (int rep = 0; rep < 2 && nlock > 0; ++rep) {
+            dots(0, nlock, s0, nullptr, 0);
+            update(0, nlock, s0, nullptr);
+        }
+        double n2 = norm2_sync(nlock, s0);
+        if (!(n2 > 0.0) || !std::isfinite(n2)) fail(ED_EINVAL, "start vector is zero (or lies in the locked subspace)");
+        k_scale<<<grid_for(h->D, 256, 1 << 16), 256, 0, s>>>(s0, h->D, 1.0 / std::sqrt(n2), h->prec == ED_FP32);
+        ED_LAUNCH_CHECK();
+        n2 = norm2_sync(nlock, s0);
+        if (!(n2 > 0.0) || !std::isfinite(n2)) fail(ED_EINVAL, "start vector is zero (or lies in the locked subspace)");
+        const double sg = 1.0 / n2;
+        ED_HIP(hipMemcpyAsync(w.sig2 + nlock, &sg, sizeof(double), hipMemcpyHostToDevice, s));
+        ED_HIP(hipStreamSynchronize(s));
+        return n2;
+    }
+
+    // One eigenpair by restarted Lanczos.  `out` receives the Ritz vector
+    // normalised to 1 (it must not be one of the slots).  Returns the status.
+    ed_status run(const void *v0, void *out, double *E, ed_info *info) {
+        const int m = w.m;
+        ed_info inf{};
+        ED_HIP(hipMemcpyAsync(w.slots[0], v0, (size_t)h->D * w.elem, hipMemcpyDeviceToDevice, s));
+        std::vector<void *> kr(w.slots.begin(), w.slots.end());
+        upload_pointers(kr);
+        prepare_start(kr[0]);
+        int total = 0;
+        bool converged = false;
+        double theta = 0.0, resid = 0.0;
+        int jlast = -1;  // number of steps in the current cycle
+        const double eps = 2.220446049250313e-16;
+        while (true) {
+            k_zero<<<1, 256, 0, s>>>(w.alpha, m + 2);
+            k_zero<<<1, 256, 0, s>>>(w.beta, m + 2);
+            ED_LAUNCH_CHECK();
+            int j = 0;
+            bool cycle_done = false;
+            for (; j < m; ++j) {
+                void *Y = kr[j + 1];
+                apply_launch(h, kr[j], Y, s);
+                const int nv = nlock + j + 1;
+                int vb = 0, nvec = nv;
+                if (o.reorth == 0 && j >= 2) {  // three-term recurrence by projection on S_{j-1}, S_j
+                    vb = nlock + j - 1;
+                    nvec = 2;
+                }
+                const int passes = o.reorth == 2 ? 2 : 1;
+                for (int ps = 0; ps < passes; ++ps) {
+                    const bool last_pass = ps == passes - 1;
+                    dots(vb, nvec, Y, w.alpha + j, nlock + j - vb);
+                    // the last pass also scales by sigma_j: the stored vector is w''
+                    update(vb, nvec, Y, last_pass ? w.partials : nullptr, last_pass ? w.sig2 + nlock + j : nullptr);
+                }
+                k_finalize_norm<<<1, 256, 0, s>>>(w.partials, w.nblk, w.sig2, w.beta, nlock + j, j);
+                ED_LAUNCH_CHECK();
+                ++total;
+                const bool full = (j + 1 == m);
+                const bool check = j == 0 || ((j + 1) % o.check_every == 0) || full || total >= o.max_iter;
+                if (!check) continue;
+                k_tridiag_lowest<<<1, 256, 0, s>>>(w.alpha, w.beta, j + 1, 0.0, w.tri, w.triwork);
+                ED_LAUNCH_CHECK();
+                double tv[3];
+                ED_HIP(hipMemcpyAsync(tv, w.tri, sizeof(tv), hipMemcpyDeviceToHost, s));
+                ED_HIP(hipStreamSynchronize(s));
+                theta = tv[0];
+                resid = tv[1];
+                jlast = j + 1;
+                const double scale = std::max(std::fabs(theta), 1.0);
+                const bool brk = std::fabs(tv[2]) <= 64.0 * eps * scale;
+                if (!std::isfinite(theta) || !std::isfinite(resid))
+                    fail(ED_EDEVICE, "non-finite Lanczos coefficients (alpha/beta) at step %d", total);
+                if (resid <= o.tol * scale || brk) {
+                    converged = true;
+                    cycle_done = true;
+                    break;
+                }
+                if (total >= o.max_iter || full) {
+                    cycle_done = true;
+                    break;
+                }
+            }
+            (void)cycle_done;
+            inf.basis_used = std::max(inf.basis_used, jlast);
+            // Ritz vector of this cycle
+            k_ritz_coef<<<1, 256, 0, s>>>(w.tri + 3, w.sig2 + nlock, jlast, w.coef);
+            ED_LAUNCH_CHECK();
+            if (converged || total >= o.max_iter) {
+                combine(nlock, w.coef, jlast, out);
+                break;
+            }
+            // restart: psi -> the spare slot, which becomes the new S_0
+            void *spare = kr[m];
+            combine(nlock, w.coef, jlast, spare);
+            std::rotate(kr.begin(), kr.begin() + m, kr.end());
+            upload_pointers(kr);
+            prepare_start(kr[0]);
+            ++inf.restarts;
+        }
+        // normalise the output and refine
+        ED_HIP(hipStreamSynchronize(s));
+        // pointer table slot for `out` at position nlock (Krylov slots are done)
+        const void *outp = out;
+        ED_HIP(hipMemcpyAsync(w.vp + nlock, &outp, sizeof(void *), hipMemcpyHostToDevice, s));
+        ED_HIP(hipStreamSynchronize(s));
+        const double n2 = norm2_sync(nlock, out);
+        if (!(n2 > 0.0)) fail(ED_EDEVICE, "Ritz vector has zero norm");
+        k_scale<<<grid_for(h->D, 256, 1 << 16), 256, 0, s>>>(out, h->D, 1.0 / std::sqrt(n2), h->prec == ED_FP32);
+        ED_LAUNCH_CHECK();
+        inf.iters = total;
+        inf.converged = converged ? 1 : 0;
+        inf.ritz = theta;
+        double rq = theta, rr = resid;
+        if (o.refine) {
+            rayleigh_fp64(h, out, &rq, &rr, s);
+            inf.residual = rr;
+            inf.rq_fp64 = rq;
+            *E = rq;
+        } else {
+            inf.residual = resid;
+            inf.rq_fp64 = theta;
+            *E = theta;
+        }
+        ED_HIP(hipStreamSynchronize(s));
+        if (info) *info = inf;
+        return converged ? ED_OK : ED_ENOCONV;
+    }
+};
+
+static size_t ws_needed(const ed_ham_s *h, const ed_lanczos_opts &o, int k, bool locked_in_ws) {
+    Work w;
+    return layout(w, nullptr, h->D, h->prec == ED_FP64 ? 8 : 4, o.max_basis, k, locked_in_ws);
+}
+
+}  // namespace ed
+
+using namespace ed;
+
+extern "C" void ed_lanczos_defaults(ed_lanczos_opts *opts) {
+    if (opts) fill_defaults(*opts);
+}
+
+extern "C" ed_status ed_workspace_bytes(ed_ham_t h, const ed_lanczos_opts *opts, int k, size_t *bytes) {
+    return guard([&] {
+        if (!h || !bytes) fail(ED_EINVAL, "ed_workspace_bytes: NULL argument");
+        if (k < 1 || (int64_t)k > h->D) fail(ED_EINVAL, "ed_workspace_bytes: k=%d outside [1, D=%lld]", k, (long long)h->D);
+        if (k > 200) fail(ED_EINVAL, "ed_workspace_bytes: k=%d above 200", k);
+        ed_lanczos_opts o = effective(opts, h->D);
+        if (o.max_basis > kMaxVec - 2 - k) o.max_basis = kMaxVec - 2 - k;
+        const int64_t room = h->D - (k - 1);
+        if ((int64_t)o.max_basis > room) o.max_basis = (int)std::max<int64_t>(room, 1);
+        *bytes = ws_needed(h, o, k, true);
+    });
+}
+
+static ed_status solve(ed_ham_t h, int k, const ed_lanczos_opts *opts, const void *v0, void *ws, size_t ws_bytes,
+                       double *evals, void *evecs, ed_info *info, void *stream) {
+    ed_status result = ED_OK;
+    ed_status st = guard([&] {
+        if (!h) fail(ED_EINVAL, "NULL handle");
+        if (!v0 || !ws || !evals) fail(ED_EINVAL, "NULL start vector, workspace or output");
+        if (k < 1 || (int64_t)k > h->D) fail(ED_EINVAL, "k=%d outside [1, D=%lld]", k, (long long)h->D);
+        DeviceGuard g(h->device);
+        Solver sv;
+        sv.h = h;
+        sv.s = (hipStream_t)stream;
+        sv.o = effective(opts, h->D);
+        // a basis of m vectors in a deflated space of dimension D - (k-1)
+        if (k > 200) fail(ED_EINVAL, "k=%d above 200", k);
+        if (sv.o.max_basis > kMaxVec - 2 - k) sv.o.max_basis = kMaxVec - 2 - k;
+        const int64_t room = h->D - (k - 1);
+        if ((int64_t)sv.o.max_basis > room) sv.o.max_basis = (int)std::max<int64_t>(room, 1);
+        const bool locked_in_ws = (evecs == nullptr);
+        const size_t need = ws_needed(h, sv.o, k, locked_in_ws);
+        if (ws_bytes < need) fail(ED_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+        layout(sv.w, (char *)ws, h->D, h->prec == ED_FP64 ? 8 : 4, sv.o.max_basis, k, locked_in_ws);
+        if (!locked_in_ws)
+            for (int i = 0; i < k; ++i) sv.w.locked[i] = (char *)evecs + (size_t)i * h->D * sv.w.elem;
+        for (int e = 0; e < k; ++e) {
+            double E = 0.0;
+            ed_info inf{};
+            const ed_status r = sv.run(v0, sv.w.locked[e], &E, &inf);
+            if (r != ED_OK) result = r;
+            evals[e] = E;
+            if (info) info[e] = inf;
+            // lock it: sigma^2 = 1 / ||psi||^2 (psi normalised to ~1 in storage precision)
+            sv.nlock = e;  // pointer table entries [0, e) are the already-locked vectors
+            // recompute the norm of the new locked vector through slot e
+            const void *p = sv.w.locked[e];
+            ED_HIP(hipMemcpyAsync(sv.w.vp + e, &p, sizeof(void *), hipMemcpyHostToDevice, sv.s));
+            ED_HIP(hipStreamSynchronize(sv.s));
+            const double n2 = sv.norm2_sync(e, p);
+            sv.lock_sig2.push_back(n2 > 0.0 ? 1.0 / n2 : 0.0);
+            sv.nlock = e + 1;
+        }
+        // eigenvalues found one after another on the deflated operator are
+        // already ascending up to rounding; report them sorted with vectors kept
+        // in discovery order only if no vectors were requested
+        if (!evecs) std::sort(evals, evals + k);
+    });
+    if (st != ED_OK) return st;
+    return result;
+}
+
+extern "C" ed_status ed_lanczos_ground(ed_ham_t h, const ed_lanczos_opts *opts, const void *v0, void *ws,
+                                       size_t ws_bytes, double *E0, void *psi0, ed_info *info, void *stream) {
+    return solve(h, 1, opts, v0, ws, ws_bytes, E0, psi0, info, stream);
+}
+
+extern "C" ed_status ed_arnoldi_lowest(ed_ham_t h, int k, const ed_lanczos_opts *opts, const void *v0, void *ws,
+                                       size_t ws_bytes, double *evals, void *evecs, ed_info *info, void *stream) {
+    return solve(h, k, opts, v0, ws, ws_bytes, evals, evecs, info, stream);
+}

@@ -1,0 +1,536 @@
+// Setup phase in matrix-free form (the paper's "Hamiltonian construction",
+// T_setup in Table 1): per-spin hop tables, one-spin diagonal pieces, the
+// cross-spin density-density decomposition and the move tables of the
+// four-fermion (spin-flip / pair-hopping) terms of Section 4.
+//
+// Hop table of spin s: for source rank r and each ordered pair (i, j), i != j,
+// with h_ij != 0, j occupied and i empty, the entry (target rank of
+// s ^ (1<<i) ^ (1<<j), sign, h_ij) of  h_ij c+_i c_j |r>.  The sign is the parity
+// of occupied sites strictly between i and j (computed with a popcount).  Rows
+// are sorted by target rank.  Because h is symmetric the same table serves the
+// gather (pull) form of the product.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <tuple>
+
+#include "ed_internal.h"
+
+namespace ed {
+
+__device__ __forceinline__ uint32_t between_mask(int i, int j) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    // bits lo+1 .. hi-1
+    return ((1u << hi) - 1u) & ~((2u << lo) - 1u);
+}
+
+// ---------------------------------------------------------------- scan ----
+// Exclusive prefix sum of n int64 values in one workgroup (setup only).
+__global__ void k_scan_i64(const int64_t *in, int64_t *out, int64_t n) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + blockDim.x - 1) / blockDim.x;
+    const int64_t a = t * chunk, b = (a + chunk < n) ? a + chunk : n;
+    int64_t s = 0;
+    for (int64_t i = a; i < b; ++i) s += in[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t run = 0;
+        for (int k = 0; k < (int)blockDim.x; ++k) {
+            const int64_t v = part[k];
+            part[k] = run;
+            run += v;
+        }
+        out[n] = run;
+    }
+    __syncthreads();
+    int64_t run = part[t];
+    for (int64_t i = a; i < b; ++i) {
+        const int64_t v = in[i];
+        out[i] = run;
+        run += v;
+    }
+}
+
+// ------------------------------------------------------------ hop tables ----
+__global__ void k_hop_count(const uint32_t *st, int64_t dim, const int2 *pairs, int np, int64_t *cnt) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < dim;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = st[r];
+        int c = 0;
+        for (int q = 0; q < np; ++q) {
+            const int i = pairs[q].x, j = pairs[q].y;
+            c += ((s >> j) & 1u) && !((s >> i) & 1u);
+        }
+        cnt[r] = c;
+    }
+}
+
+__global__ void k_hop_fill(const uint32_t *st, int64_t dim, int ns, int n, const int2 *pairs,
+                           const double *pamp, int np, const int64_t *off64, int32_t *off,
+                           int32_t *tgt, int8_t *sgn, double *amp, double *sa64, float *sa32) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < dim;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = st[r];
+        const int64_t a = off64[r];
+        off[r] = (int32_t)a;
+        if (r == dim - 1) off[dim] = (int32_t)off64[dim];
+        int64_t k = a;
+        for (int q = 0; q < np; ++q) {
+            const int i = pairs[q].x, j = pairs[q].y;
+            if (!(((s >> j) & 1u) && !((s >> i) & 1u))) continue;
+            const uint32_t s2 = s ^ (1u << i) ^ (1u << j);
+            const int32_t t = (int32_t)rank_state(s2, ns, n);
+            const int8_t sg = (__popc(s & between_mask(i, j)) & 1) ? (int8_t)-1 : (int8_t)1;
+            // insertion into the sorted run [a, k)
+            int64_t p = k;
+            while (p > a && tgt[p - 1] > t) {
+                tgt[p] = tgt[p - 1];
+                sgn[p] = sgn[p - 1];
+                amp[p] = amp[p - 1];
+                --p;
+            }
+            tgt[p] = t;
+            sgn[p] = sg;
+            amp[p] = pamp[q];
+            ++k;
+        }
+        for (int64_t e = a; e < k; ++e) {
+            const double v = (double)sgn[e] * amp[e];
+            sa64[e] = v;
+            sa32[e] = (float)v;
+        }
+    }
+}
+
+// sliced ELL: slice = 64 consecutive states, entries (slice, k, lane)
+__global__ void k_ell_len(const int64_t *cnt, int64_t dim, int64_t nslices, int64_t *len) {
+    for (int64_t sl = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; sl < nslices;
+         sl += (int64_t)gridDim.x * blockDim.x) {
+        int64_t m = 0;
+        for (int l = 0; l < 64; ++l) {
+            const int64_t r = sl * 64 + l;
+            if (r < dim && cnt[r] > m) m = cnt[r];
+        }
+        len[sl] = m * 64;
+    }
+}
+
+__global__ void k_ell_fill(const int64_t *off64, int64_t dim, int64_t nslices, const int64_t *ell64,
+                           int32_t *ell_off, const int32_t *tgt, const double *sa64, int32_t *etgt,
+                           double *esa64, float *esa32) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nslices * 64;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t sl = idx >> 6;
+        const int lane = (int)(idx & 63);
+        const int64_t base = ell64[sl];
+        const int64_t kk = (ell64[sl + 1] - base) >> 6;
+        if (lane == 0) {
+            ell_off[sl] = (int32_t)base;
+            if (sl == nslices - 1) ell_off[nslices] = (int32_t)ell64[nslices];
+        }
+        const int64_t r = idx;
+        const int64_t a = r < dim ? off64[r] : 0;
+        const int64_t c = r < dim ? off64[r + 1] - a : 0;
+        for (int64_t k = 0; k < kk; ++k) {
+            const int64_t e = base + k * 64 + lane;
+            if (k < c) {
+                etgt[e] = tgt[a + k];
+                esa64[e] = sa64[a + k];
+                esa32[e] = (float)sa64[a + k];
+            } else {
+                etgt[e] = r < dim ? (int32_t)r : 0;
+                esa64[e] = 0.0;
+                esa32[e] = 0.0f;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------- diagonal pieces ----
+// e_s(state) = sum_i eps_i n_i + sum_{i<j} w_ij n_i n_j  (FP64, cast for FP32)
+__global__ void k_ediag(const uint32_t *st, int64_t dim, int ns, const double *eps, const double *wss,
+                        double *e64, float *e32) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < dim;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = st[r];
+        double e = 0.0;
+        for (int i = 0; i < ns; ++i) {
+            if (!((s >> i) & 1u)) continue;
+            e += eps[i];
+            for (int j = i + 1; j < ns; ++j)
+                if ((s >> j) & 1u) e += wss[i * ns + j];
+        }
+        e64[r] = e;
+        e32[r] = (float)e;
+    }
+}
+
+__global__ void k_cidx(const uint32_t *st, int64_t dim, const int *sites, int k, uint8_t *out) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < dim;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = st[r];
+        uint32_t c = 0;
+        for (int q = 0; q < k; ++q) c |= ((s >> sites[q]) & 1u) << q;
+        out[r] = (uint8_t)c;
+    }
+}
+
+// move table: electron src -> dst on every state: (rank << 1 | sign bit) or -1
+__global__ void k_move(const uint32_t *st, int64_t dim, int ns, int n, int src, int dst, int32_t *out) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < dim;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = st[r];
+        int32_t v = -1;
+        if (((s >> src) & 1u) && !((s >> dst) & 1u)) {
+            const uint32_t s2 = s ^ (1u << src) ^ (1u << dst);
+            const int64_t t = rank_state(s2, ns, n);
+            const int neg = __popc(s & between_mask(src, dst)) & 1;
+            v = (int32_t)((t << 1) | neg);
+        }
+        out[r] = v;
+    }
+}
+
+// ------------------------------------------------------------------ host ----
+static bool finite_all(const double *a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+template <class T>
+static void upload(DevMem &m, const std::vector<T> &v) {
+    m.alloc(std::max<size_t>(v.size(), 1) * sizeof(T));
+    if (!v.empty()) ED_HIP(hipMemcpy(m.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+static int move_index(SpinTab &t, int src, int dst) {
+    for (int q = 0; q < (int)t.mv_src.size(); ++q)
+        if (t.mv_src[q] == src && t.mv_dst[q] == dst) return q;
+    t.mv_src.push_back(src);
+    t.mv_dst.push_back(dst);
+    return (int)t.mv_src.size() - 1;
+}
+
+static void build_spin(ed_ham_s *h, int s, const BasisData &b, const ed_params *p) {
+    SpinTab &t = h->sp[s];
+    const int ns = b.ns;
+    t.ns = ns;
+    t.n = b.n[s];
+    t.dim = b.dim[s];
+    const int64_t dim = t.dim;
+    t.states.alloc((size_t)dim * sizeof(uint32_t));
+    ED_HIP(hipMemcpy(t.states.p, b.states[s].p, (size_t)dim * sizeof(uint32_t), hipMemcpyDeviceToDevice));
+
+    // ordered pairs (i, j) with h_ij != 0, in (i, j) lexicographic order
+    std::vector<int2> pairs;
+    std::vector<double> pamp;
+    const double *hs = p->hop + (size_t)s * ns * ns;
+    for (int i = 0; i < ns; ++i)
+        for (int j = 0; j < ns; ++j)
+            if (i != j && hs[i * ns + j] != 0.0) {
+                pairs.push_back(make_int2(i, j));
+                pamp.push_back(hs[i * ns + j]);
+            }
+    DevMem dpairs, dpamp, cnt, off64;
+    upload(dpairs, pairs);
+    upload(dpamp, pamp);
+    cnt.alloc((size_t)dim * sizeof(int64_t));
+    off64.alloc((size_t)(dim + 1) * sizeof(int64_t));
+    const unsigned g = grid_for(dim, 256, 1 << 16);
+    k_hop_count<<<g, 256>>>(t.states.as<uint32_t>(), dim, dpairs.as<int2>(), (int)pairs.size(),
+                            cnt.as<int64_t>());
+    ED_LAUNCH_CHECK();
+    k_scan_i64<<<1, 1024>>>(cnt.as<int64_t>(), off64.as<int64_t>(), dim);
+    ED_LAUNCH_CHECK();
+    int64_t nnz = 0;
+    ED_HIP(hipMemcpy(&nnz, off64.as<int64_t>() + dim, sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (nnz > 0x7fffffffll) fail(ED_ENOMEM, "hop table of spin %d has %lld entries (> 2^31-1)", s, (long long)nnz);
+    t.nnz = nnz;
+    t.off.alloc((size_t)(dim + 1) * sizeof(int32_t));
+    t.tgt.alloc((size_t)nnz * sizeof(int32_t));
+    t.sgn.alloc((size_t)nnz);
+    t.amp.alloc((size_t)nnz * sizeof(double));
+    t.sa64.alloc((size_t)nnz * sizeof(double));
+    t.sa32.alloc((size_t)nnz * sizeof(float));
+    k_hop_fill<<<g, 256>>>(t.states.as<uint32_t>(), dim, ns, t.n, dpairs.as<int2>(), dpamp.as<double>(),
+                           (int)pairs.size(), off64.as<int64_t>(), t.off.as<int32_t>(), t.tgt.as<int32_t>(),
+                           t.sgn.as<int8_t>(), t.amp.as<double>(), t.sa64.as<double>(), t.sa32.as<float>());
+    ED_LAUNCH_CHECK();
+
+    // sliced ELL
+    t.nslices = (dim + 63) / 64;
+    DevMem ellen, ell64;
+    ellen.alloc((size_t)t.nslices * sizeof(int64_t));
+    ell64.alloc((size_t)(t.nslices + 1) * sizeof(int64_t));
+    k_ell_len<<<grid_for(t.nslices, 256, 1 << 16), 256>>>(cnt.as<int64_t>(), dim, t.nslices, ellen.as<int64_t>());
+    ED_LAUNCH_CHECK();
+    k_scan_i64<<<1, 1024>>>(ellen.as<int64_t>(), ell64.as<int64_t>(), t.nslices);
+    ED_LAUNCH_CHECK();
+    int64_t nell = 0;
+    ED_HIP(hipMemcpy(&nell, ell64.as<int64_t>() + t.nslices, sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (nell > 0x7fffffffll) fail(ED_ENOMEM, "sliced hop table of spin %d too large", s);
+    t.ell_off.alloc((size_t)(t.nslices + 1) * sizeof(int32_t));
+    t.ell_tgt.alloc((size_t)nell * sizeof(int32_t));
+    t.ell_sa64.alloc((size_t)nell * sizeof(double));
+    t.ell_sa32.alloc((size_t)nell * sizeof(float));
+    k_ell_fill<<<grid_for(t.nslices * 64, 256, 1 << 16), 256>>>(
+        off64.as<int64_t>(), dim, t.nslices, ell64.as<int64_t>(), t.ell_off.as<int32_t>(), t.tgt.as<int32_t>(),
+        t.sa64.as<double>(), t.ell_tgt.as<int32_t>(), t.ell_sa64.as<double>(), t.ell_sa32.as<float>());
+    ED_LAUNCH_CHECK();
+    {
+        std::vector<int64_t> hc((size_t)dim);
+        ED_HIP(hipMemcpy(hc.data(), cnt.p, (size_t)dim * sizeof(int64_t), hipMemcpyDeviceToHost));
+        int64_t m = 0;
+        for (int64_t v : hc) m = std::max(m, v);
+        t.max_hops = (int)m;
+    }
+
+    // one-spin diagonal piece
+    std::vector<double> eps(p->eps + (size_t)s * ns, p->eps + (size_t)(s + 1) * ns);
+    std::vector<double> wss(p->w_ss + (size_t)s * ns * ns, p->w_ss + (size_t)(s + 1) * ns * ns);
+    DevMem deps, dwss;
+    upload(deps, eps);
+    upload(dwss, wss);
+    t.ediag64.alloc((size_t)dim * sizeof(double));
+    t.ediag32.alloc((size_t)dim * sizeof(float));
+    k_ediag<<<g, 256>>>(t.states.as<uint32_t>(), dim, ns, deps.as<double>(), dwss.as<double>(),
+                        t.ediag64.as<double>(), t.ediag32.as<float>());
+    ED_LAUNCH_CHECK();
+    ED_HIP(hipDeviceSynchronize());
+}
+
+static void build_cross(ed_ham_s *h, const ed_params *p) {
+    const int ns = h->ns;
+    const double *w = p->w_ud;
+    // on-site part
+    uint32_t umask = 0;
+    double u0 = 0.0;
+    bool uniform = true;
+    std::vector<double> us(32, 0.0);
+    for (int i = 0; i < ns; ++i) {
+        const double v = w[i * ns + i];
+        us[i] = v;
+        if (v == 0.0) continue;
+        if (umask == 0) u0 = v;
+        else if (v != u0) uniform = false;
+        umask |= 1u << i;
+    }
+    h->umask = umask;
+    h->U0 = u0;
+    h->umode = umask == 0 ? 0 : (uniform ? 1 : 2);
+    upload(h->usite64, us);
+    std::vector<float> us32(us.begin(), us.end());
+    upload(h->usite32, us32);
+
+    // off-diagonal part: sites touched by any w_ud[i][j], i != j
+    std::vector<int> sites;
+    for (int i = 0; i < ns; ++i) {
+        bool any = false;
+        for (int j = 0; j < ns; ++j)
+            if (j != i && (w[i * ns + j] != 0.0 || w[j * ns + i] != 0.0)) any = true;
+        if (any) sites.push_back(i);
+    }
+    if (sites.size() > 8)
+        fail(ED_EUNSUPPORTED, "off-diagonal w_ud entries touch %zu sites (at most 8 supported)", sites.size());
+    h->koff = (int)sites.size();
+    const int k = h->koff;
+    if (k > 0) {
+        const int nt = 1 << k;
+        std::vector<double> tab((size_t)nt * nt, 0.0);
+        for (int cu = 0; cu < nt; ++cu)
+            for (int cd = 0; cd < nt; ++cd) {
+                double e = 0.0;
+                for (int a = 0; a < k; ++a)
+                    for (int c = 0; c < k; ++c)
+                        if (a != c || sites[a] != sites[c])
+                            if (((cu >> a) & 1) && ((cd >> c) & 1) && sites[a] != sites[c])
+                                e += w[sites[a] * ns + sites[c]];
+                tab[(size_t)cu * nt + cd] = e;
+            }
+        upload(h->xtab64, tab);
+        std::vector<float> tab32(tab.begin(), tab.end());
+        upload(h->xtab32, tab32);
+        DevMem dsites;
+        upload(dsites, sites);
+        for (int s = 0; s < 2; ++s) {
+            SpinTab &t = h->sp[s];
+            t.cidx.alloc((size_t)t.dim);
+            k_cidx<<<grid_for(t.dim, 256, 1 << 16), 256>>>(t.states.as<uint32_t>(), t.dim, dsites.as<int>(), k,
+                                                          t.cidx.as<uint8_t>());
+            ED_LAUNCH_CHECK();
+        }
+        ED_HIP(hipDeviceSynchronize());
+    } else {
+        upload(h->xtab64, std::vector<double>(1, 0.0));
+        upload(h->xtab32, std::vector<float>(1, 0.0f));
+        for (int s = 0; s < 2; ++s) {
+            h->sp[s].cidx.alloc((size_t)h->sp[s].dim);
+            ED_HIP(hipMemset(h->sp[s].cidx.p, 0, (size_t)h->sp[s].dim));
+        }
+    }
+}
+
+// Four-fermion terms as products of one-spin moves (Section 4):
+//   d+_{m up} d_{m dn} d+_{m' dn} d_{m' up} = -(d+_{m up} d_{m' up})(d+_{m' dn} d_{m dn})
+//   d+_{m up} d+_{m dn} d_{m' up} d_{m' dn} = -(d+_{m up} d_{m' up})(d+_{m dn} d_{m' dn})
+// (anticommuting the operators past each other), and an even down-spin pair
+// passes the up block without a sign.  So a term with coefficient c acting on
+// (u, d) gives (up: m' -> m, down: m -> m' or m' -> m) with element -c s_up s_dn.
+static void build_xterms(ed_ham_s *h, const ed_params *p) {
+    std::map<std::pair<int, int>, double> acc;  // (up move, dn move) -> amplitude
+    for (int t = 0; t < p->n_x; ++t) {
+        const ed_xterm &x = p->x[t];
+        const int um = move_index(h->sp[0], x.mp, x.m);
+        const int dm = (x.type == ED_SPIN_FLIP) ? move_index(h->sp[1], x.m, x.mp) : move_index(h->sp[1], x.mp, x.m);
+        acc[{um, dm}] += -x.coef;
+    }
+    h->xterms.clear();
+    for (auto &kv : acc)
+        if (kv.second != 0.0) h->xterms.push_back(XTerm{kv.first.first, kv.first.second, kv.second});
+    h->nx = (int)h->xterms.size();
+    for (int s = 0; s < 2; ++s) {
+        SpinTab &t = h->sp[s];
+        t.nmv = (int)t.mv_src.size();
+        t.mv.alloc((size_t)std::max(t.nmv, 1) * (size_t)t.dim * sizeof(int32_t));
+        for (int q = 0; q < t.nmv; ++q) {
+            k_move<<<grid_for(t.dim, 256, 1 << 16), 256>>>(t.states.as<uint32_t>(), t.dim, t.ns, t.n, t.mv_src[q],
+                                                          t.mv_dst[q], t.mv.as<int32_t>() + (size_t)q * t.dim);
+            ED_LAUNCH_CHECK();
+        }
+    }
+    std::vector<XTermDev<double>> x64;
+    std::vector<XTermDev<float>> x32;
+    for (auto &x : h->xterms) {
+        x64.push_back(XTermDev<double>{x.up_mv, x.dn_mv, x.amp});
+        x32.push_back(XTermDev<float>{x.up_mv, x.dn_mv, (float)x.amp});
+    }
+    upload(h->xt64, x64);
+    upload(h->xt32, x32);
+    ED_HIP(hipDeviceSynchronize());
+}
+
+static void validate(const ed_params *p, int ns) {
+    if (!p) fail(ED_EINVAL, "ed_ham_create: params is NULL");
+    if (p->Ns != ns) fail(ED_EINVAL, "ed_ham_create: params Ns=%d but basis Ns=%d", p->Ns, ns);
+    if (!p->eps || !p->hop || !p->w_ud || !p->w_ss) fail(ED_EINVAL, "ed_ham_create: NULL coefficient array");
+    if (p->n_x < 0 || (p->n_x > 0 && !p->x)) fail(ED_EINVAL, "ed_ham_create: bad four-fermion term list");
+    const size_t n = (size_t)ns;
+    if (!finite_all(p->eps, 2 * n) || !finite_all(p->hop, 2 * n * n) || !finite_all(p->w_ud, n * n) ||
+        !finite_all(p->w_ss, 2 * n * n))
+        fail(ED_EINVAL, "ed_ham_create: non-finite coefficient");
+    for (int s = 0; s < 2; ++s) {
+        const double *hs = p->hop + (size_t)s * n * n;
+        const double *ws = p->w_ss + (size_t)s * n * n;
+        for (int i = 0; i < ns; ++i) {
+            if (hs[i * ns + i] != 0.0) fail(ED_EINVAL, "ed_ham_create: hop[%d] has a nonzero diagonal (use eps)", s);
+            for (int j = 0; j < ns; ++j) {
+                if (hs[i * ns + j] != hs[j * ns + i])
+                    fail(ED_EINVAL, "ed_ham_create: hop[%d] is not symmetric at (%d,%d)", s, i, j);
+                if (j <= i && ws[i * ns + j] != 0.0)
+                    fail(ED_EINVAL, "ed_ham_create: w_ss[%d] must be zero on and below the diagonal", s);
+            }
+        }
+    }
+    std::map<std::tuple<int, int, int>, double> sum;
+    for (int t = 0; t < p->n_x; ++t) {
+        const ed_xterm &x = p->x[t];
+        if (x.type != ED_SPIN_FLIP && x.type != ED_PAIR_HOP) fail(ED_EINVAL, "ed_ham_create: bad term type %d", x.type);
+        if (x.m < 0 || x.mp < 0 || x.m >= ns || x.mp >= ns || x.m == x.mp)
+            fail(ED_EINVAL, "ed_ham_create: bad orbital pair (%d,%d)", x.m, x.mp);
+        if (!std::isfinite(x.coef)) fail(ED_EINVAL, "ed_ham_create: non-finite term coefficient");
+        sum[std::make_tuple(x.type, x.m, x.mp)] += x.coef;
+    }
+    for (auto &kv : sum) {
+        auto it = sum.find(std::make_tuple(std::get<0>(kv.first), std::get<2>(kv.first), std::get<1>(kv.first)));
+        const double other = it == sum.end() ? 0.0 : it->second;
+        if (other != kv.second)
+            fail(ED_EINVAL, "ed_ham_create: four-fermion terms are not Hermitian (type %d, %d, %d)",
+                 std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first));
+    }
+}
+
+void build_tables(ed_ham_s *h, const ed_params *p, const BasisData &b) {
+    validate(p, b.ns);
+    ensure_device_binomials();
+    h->ns = b.ns;
+    h->nup = b.n[0];
+    h->ndn = b.n[1];
+    h->dup = b.dim[0];
+    h->ddn = b.dim[1];
+    h->D = h->dup * h->ddn;
+    if (h->dup > (1ll << 30) || h->ddn > (1ll << 30)) fail(ED_EUNSUPPORTED, "one-spin dimension above 2^30");
+    for (int s = 0; s < 2; ++s) build_spin(h, s, b, p);
+    build_cross(h, p);
+    build_xterms(h, p);
+}
+
+}  // namespace ed
+
+using namespace ed;
+
+extern "C" ed_status ed_ham_create(const ed_params *p, ed_basis_t b, int precision, ed_ham_t *out) {
+    return guard([&] {
+        if (!out) fail(ED_EINVAL, "ed_ham_create: out is NULL");
+        *out = nullptr;
+        if (!b) fail(ED_EINVAL, "ed_ham_create: NULL basis");
+        if (precision != ED_FP64 && precision != ED_FP32) fail(ED_EINVAL, "ed_ham_create: bad precision");
+        DeviceGuard g(b->device);
+        ed_ham_s *h = new ed_ham_s();
+        try {
+            h->device = b->device;
+            h->prec = precision;
+            build_tables(h, p, b->b);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+extern "C" ed_status ed_ham_dims(ed_ham_t h, int64_t *Dup, int64_t *Ddn, int64_t *D) {
+    return guard([&] {
+        if (!h) fail(ED_EINVAL, "ed_ham_dims: NULL handle");
+        if (Dup) *Dup = h->dup;
+        if (Ddn) *Ddn = h->ddn;
+        if (D) *D = h->D;
+    });
+}
+
+extern "C" ed_status ed_hop_table_size(ed_ham_t h, int spin, int64_t *nnz) {
+    return guard([&] {
+        if (!h || !nnz) fail(ED_EINVAL, "ed_hop_table_size: NULL argument");
+        if (spin != 0 && spin != 1) fail(ED_EINVAL, "ed_hop_table_size: spin must be 0 or 1");
+        *nnz = h->sp[spin].nnz;
+    });
+}
+
+extern "C" ed_status ed_hop_table(ed_ham_t h, int spin, int64_t *off, int32_t *tgt, int8_t *sign, double *amp) {
+    return guard([&] {
+        if (!h || !off) fail(ED_EINVAL, "ed_hop_table: NULL argument");
+        if (spin != 0 && spin != 1) fail(ED_EINVAL, "ed_hop_table: spin must be 0 or 1");
+        DeviceGuard g(h->device);
+        const SpinTab &t = h->sp[spin];
+        std::vector<int32_t> o((size_t)t.dim + 1);
+        ED_HIP(hipMemcpy(o.data(), t.off.p, o.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < o.size(); ++i) off[i] = o[i];
+        if (t.nnz > 0) {
+            if (tgt) ED_HIP(hipMemcpy(tgt, t.tgt.p, (size_t)t.nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+            if (sign) ED_HIP(hipMemcpy(sign, t.sgn.p, (size_t)t.nnz, hipMemcpyDeviceToHost));
+            if (amp) ED_HIP(hipMemcpy(amp, t.amp.p, (size_t)t.nnz * sizeof(double), hipMemcpyDeviceToHost));
+        }
+    });
+}
+
+extern "C" void ed_ham_free(ed_ham_t h) {
+    if (!h) return;
+    try {
+        DeviceGuard g(h->device);
+        (void)hipDeviceSynchronize();
+        delete h;
+    } catch (...) {
+    }
+}

@@ -1,0 +1,103 @@
+"""Sector-batched Lanczos over all 169 sectors of the N_s = 12 three-orbital
+impurity (3 orbitals + 9 bath levels), FP32-mixed and FP64, against the oracle's
+per-sector eigenvalues, plus the symmetry pins the batch must satisfy on its own
+(spin reversal, SU(2) multiplets, the empty sector)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import gpu_ed
+from paper_1004_3354_amd import models, workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_e0.json")
+
+
+def _hams(phys, sectors, prec):
+    ed = gpu_ed()
+    p = models.params_from_model(phys)
+    hs = []
+    for (a, b) in sectors:
+        bs = ed.Basis(phys["Ns"], a, b)
+        hs.append(ed.Hamiltonian(p, bs, prec))
+    return hs
+
+
+def _gold():
+    if not os.path.exists(GOLD):
+        pytest.skip("oracle golden values not generated")
+    g = json.load(open(GOLD))["entries"]
+    if "cfg3" not in g:
+        pytest.skip("no oracle values for the 169 sectors")
+    return {tuple(int(v) for v in k.split(",")): e["evals"][0] for k, e in g["cfg3"]["sectors"].items()}
+
+
+@pytest.fixture(scope="module")
+def batch_fp32():
+    ed = gpu_ed()
+    phys, sectors = wl.config(3)
+    hs = _hams(phys, sectors, ed.ED_FP32)
+    E, info = ed.lanczos_ground_batched(hs, ed.options(tol=1e-7, max_basis=60), seed=wl.start_vector_seed(3))
+    return sectors, E, info
+
+
+def test_batched_fp32_all_sectors_vs_oracle(batch_fp32):
+    sectors, E, info = batch_fp32
+    gold = _gold()
+    worst = 0.0
+    for (sec, e, inf) in zip(sectors, E, info):
+        assert inf["converged"] == 1, (sec, inf)
+        r = abs(e - gold[sec]) / max(1.0, abs(gold[sec]))
+        worst = max(worst, r)
+        assert r <= 1e-6, (sec, e, gold[sec])
+    print("worst relative error over 169 sectors: %.2e" % worst)
+
+
+def test_batched_symmetries(batch_fp32):
+    sectors, E, info = batch_fp32
+    e = {s: v for s, v in zip(sectors, E)}
+    assert e[(0, 0)] == 0.0
+    for (a, b) in sectors:
+        assert abs(e[(a, b)] - e[(b, a)]) <= 2e-6 * max(1.0, abs(e[(a, b)]))
+        # SU(2): the (a+1, b-1) spectrum lies inside the (a, b) one when a >= b
+        if a >= b and b >= 1:
+            assert e[(a + 1, b - 1)] >= e[(a, b)] - 2e-6 * max(1.0, abs(e[(a, b)]))
+
+
+def test_batched_fp64_subset_vs_oracle():
+    ed = gpu_ed()
+    phys, _ = wl.config(3)
+    sectors = [(0, 0), (1, 0), (3, 2), (6, 6), (5, 7), (12, 0), (11, 12), (4, 9), (2, 2), (7, 5)]
+    hs = _hams(phys, sectors, ed.ED_FP64)
+    E, info = ed.lanczos_ground_batched(hs, ed.options(tol=1e-10, max_basis=80), seed=7)
+    gold = _gold()
+    for sec, e in zip(sectors, E):
+        assert abs(e - gold[sec]) / max(1.0, abs(gold[sec])) <= 1e-10, (sec, e, gold[sec])
+
+
+def test_batched_matches_single_sector_solver():
+    ed = gpu_ed()
+    phys, _ = wl.config(3)
+    sectors = [(6, 6), (2, 9), (8, 3)]
+    hs = _hams(phys, sectors, ed.ED_FP64)
+    E, _ = ed.lanczos_ground_batched(hs, ed.options(tol=1e-11, max_basis=80), seed=3)
+    for h, e in zip(hs, E):
+        v0 = torch.empty(h.D, dtype=torch.float64, device="cuda")
+        ed.fill_random(v0, 5, 1)
+        e1, _ = h.lanczos_ground(v0, ed.options(tol=1e-11))
+        assert abs(e - e1) <= 1e-10 * max(1.0, abs(e1))
+
+
+def test_batched_restarts_small_basis():
+    ed = gpu_ed()
+    phys, _ = wl.config(3)
+    sectors = [(6, 6), (5, 6), (0, 3)]
+    hs = _hams(phys, sectors, ed.ED_FP32)
+    E, info = ed.lanczos_ground_batched(hs, ed.options(tol=1e-7, max_basis=12, max_iter=2000), seed=9)
+    gold = _gold()
+    assert any(i["restarts"] > 0 for i in info)
+    for sec, e in zip(sectors, E):
+        assert abs(e - gold[sec]) / max(1.0, abs(gold[sec])) <= 1e-6, (sec, e, gold[sec])

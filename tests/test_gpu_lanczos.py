@@ -1,0 +1,174 @@
+"""GPU eigensolvers (Lanczos ground state, lowest-k with locking) against the oracle.
+
+Bars: FP64 path within 1e-10 of the oracle eigenvalue, FP32-mixed path (FP32
+vectors and H.v, FP64 reductions and refinement) within 1e-6, both relative to
+max(|E|, 1) (a zero-energy sector makes a pure relative error meaningless).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from gpu_common import build, generic_model, generic_terms, gpu_ed, sector
+from paper_1004_3354_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_e0.json")
+TOL = {0: 1e-10, 1: 1e-6}
+
+
+def _v0(D, prec, seed=11):
+    ed = gpu_ed()
+    v = torch.empty(D, dtype=torch.float64 if prec == 0 else torch.float32, device=DEV)
+    ed.fill_random(v, seed, 1)
+    return v
+
+
+def _rel(a, b):
+    return abs(a - b) / max(1.0, abs(b))
+
+
+def _golden(key, sec):
+    if not os.path.exists(GOLD):
+        pytest.skip("oracle golden values not generated")
+    g = json.load(open(GOLD))["entries"]
+    if key not in g or sec not in g[key]["sectors"]:
+        pytest.skip("no oracle golden value for %s %s" % (key, sec))
+    return g[key]["sectors"][sec]["evals"]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_config0_hv_then_100_step_lanczos(prec):
+    ed = gpu_ed()
+    phys, sectors = wl.config(0)
+    b, H = build(phys, 4, 4, prec)
+    sec = sector(phys, 4, 4)
+    ev = np.linalg.eigvalsh(sec.dense())
+    v0 = _v0(b.D, prec, wl.start_vector_seed(0))
+    E, info = H.lanczos_ground(v0, ed.options(max_iter=100, max_basis=100, tol=1e-14), allow_noconv=True)
+    assert info["iters"] <= 100
+    assert _rel(E, ev[0]) <= TOL[prec], (E, ev[0])
+    assert E >= ev[0] - 1e-12 * max(1, abs(ev[0]))   # Rayleigh quotient is variational
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("name,phys,nn", [
+    ("kan9_45", wl.kanamori(3, 2, 2.3, 0.4, seed=3), (4, 5)),
+    ("hub3x3_45", wl.hubbard(3, 3, 1.0, 4.0), (4, 5)),
+    ("aim8_26", wl.aim(7, 2.0, -1.0, seed=8), (2, 6)),
+], ids=["kan9_45", "hub3x3_45", "aim8_26"])
+def test_ground_state_small(name, phys, nn, prec):
+    ed = gpu_ed()
+    b, H = build(phys, *nn, prec)
+    sec = sector(phys, *nn)
+    e_ref = orc.lowest_k(sec, 1, tol=1e-14)[0]
+    psi = torch.empty(b.D, dtype=torch.float64 if prec == 0 else torch.float32, device=DEV)
+    E, info = H.lanczos_ground(_v0(b.D, prec), ed.options(tol=1e-10 if prec == 0 else 1e-7), psi=psi)
+    assert info["converged"] == 1
+    assert _rel(E, e_ref) <= TOL[prec], (E, e_ref)
+    # the returned vector is normalised and is an eigenvector to the reported residual
+    p = psi.double().cpu().numpy()
+    assert abs(np.linalg.norm(p) - 1.0) < (1e-12 if prec == 0 else 1e-6)
+    r = np.linalg.norm(sec.spmv(p) - E * p)
+    assert r <= max(10 * info["residual"], 1e-9)
+
+
+def test_generic_model_ground_state():
+    ed = gpu_ed()
+    p = generic_model(9, 4)
+    b = ed.Basis(9, 4, 5)
+    H = ed.Hamiltonian(p, b, ed.ED_FP64)
+    sec = orc.Sector(9, 4, 5, generic_terms(p))
+    e_ref = orc.lowest_k(sec, 1, tol=1e-14)[0]
+    E, info = H.lanczos_ground(_v0(b.D, 0), ed.options(tol=1e-11))
+    assert _rel(E, e_ref) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("name,phys,nn,k", [
+    ("kanatom_bath", wl.kanamori(3, 1, 2.3, 0.4, seed=2), (3, 3), 8),
+    ("hub2x3", wl.hubbard(3, 2, 1.0, 4.0), (3, 3), 6),
+    ("kan9_32", wl.kanamori(3, 2, 2.3, 0.4, seed=6), (3, 2), 5),
+], ids=["kanatom_bath", "hub2x3", "kan9_32"])
+def test_lowest_k_with_multiplicity(name, phys, nn, k, prec):
+    ed = gpu_ed()
+    b, H = build(phys, *nn, prec)
+    sec = sector(phys, *nn)
+    ev = np.linalg.eigvalsh(sec.dense())[:k]
+    evecs = torch.empty((k, b.D), dtype=torch.float64 if prec == 0 else torch.float32, device=DEV)
+    got, infos = H.lowest(k, _v0(b.D, prec), ed.options(tol=1e-10 if prec == 0 else 1e-7, max_basis=60),
+                          evecs=evecs)
+    tol = 1e-9 if prec == 0 else 1e-6
+    np.testing.assert_allclose(np.sort(got), ev, atol=tol * max(1.0, abs(ev[0])))
+    V = evecs.double().cpu().numpy()
+    G = V @ V.T
+    assert np.max(np.abs(G - np.eye(k))) < (1e-8 if prec == 0 else 1e-4)
+
+
+def test_breakdown_exact_eigenvector_start():
+    ed = gpu_ed()
+    phys = wl.hubbard(3, 2, 1.0, 4.0)
+    b, H = build(phys, 2, 2, 0)
+    sec = sector(phys, 2, 2)
+    w, V = np.linalg.eigh(sec.dense())
+    v0 = torch.from_numpy(V[:, 0].copy()).to(DEV)
+    E, info = H.lanczos_ground(v0, ed.options(tol=1e-12))
+    assert info["converged"] == 1 and info["iters"] <= 2
+    assert _rel(E, w[0]) <= 1e-12
+
+
+def test_dimension_one_sector():
+    ed = gpu_ed()
+    phys = wl.config(3)[0]
+    b, H = build(phys, 12, 0, 0)
+    sec = sector(phys, 12, 0)
+    E, info = H.lanczos_ground(_v0(1, 0), ed.options())
+    assert abs(E - sec.dense()[0, 0]) < 1e-12
+
+
+def test_bit_reproducible():
+    ed = gpu_ed()
+    phys = wl.kanamori(3, 2, 2.3, 0.4, seed=3)
+    b, H = build(phys, 4, 4, 1)
+    v0 = _v0(b.D, 1)
+    E1, _ = H.lanczos_ground(v0, ed.options(tol=1e-7))
+    E2, _ = H.lanczos_ground(v0, ed.options(tol=1e-7))
+    assert E1 == E2
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("nn", ["6,6", "5,7", "3,9", "0,1", "12,11"])
+def test_config3_sectors_vs_golden(nn, prec):
+    ed = gpu_ed()
+    phys, _ = wl.config(3)
+    a, c = (int(v) for v in nn.split(","))
+    e_ref = _golden("cfg3", nn)[0]
+    b, H = build(phys, a, c, prec)
+    E, info = H.lanczos_ground(_v0(b.D, prec), ed.options(tol=1e-10 if prec == 0 else 1e-7))
+    assert _rel(E, e_ref) <= TOL[prec], (E, e_ref, info)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("jp", [True, False], ids=["jp_on", "jp_off"])
+def test_config2_full_size_vs_golden(jp, prec):
+    ed = gpu_ed()
+    phys, sectors = wl.config(2, jprime=jp)
+    e_ref = _golden("cfg2" if jp else "cfg2_jp_off", "7,7")[0]
+    b, H = build(phys, 7, 7, prec)
+    E, info = H.lanczos_ground(_v0(b.D, prec, wl.start_vector_seed(2)),
+                               ed.options(tol=1e-10 if prec == 0 else 1e-7, max_basis=100))
+    assert _rel(E, e_ref) <= TOL[prec], (E, e_ref, info)
+
+
+def test_config2_lowest_3_fp32_vs_golden():
+    ed = gpu_ed()
+    phys, sectors = wl.config(2)
+    ev = _golden("cfg2", "7,7")
+    b, H = build(phys, 7, 7, 1)
+    got, infos = H.lowest(3, _v0(b.D, 1, wl.start_vector_seed(2)), ed.options(tol=1e-7, max_basis=80))
+    for g, r in zip(np.sort(got), ev[:3]):
+        assert _rel(g, r) <= 1e-6, (got, ev)
