@@ -37,9 +37,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload):
+def traffic_from_profile(workload, schedule):
     """HBM bytes per launch measured by rocprofv3 counters for this exact kernel
-    source (profiles/apply_traffic.json), else None."""
+    source and schedule (profiles/apply_traffic.json), else None."""
     p = os.path.join(ROOT, "profiles", "apply_traffic.json")
     if not os.path.exists(p):
         return None
@@ -48,7 +48,7 @@ def traffic_from_profile(workload):
     except ValueError:
         return None
     e = d.get(workload)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash() or e.get("schedule") != schedule:
         return None
     return e.get("bytes_per_launch")
 
@@ -117,36 +117,35 @@ def cpu_baseline(cfg, target_s=12.0):
 
 
 def time_to_e0(cfg, precs, max_basis, tol, seed_idx):
+    """Same start vector (SplitMix64 normal stream, FP32 = RNE cast of the FP64
+    values, filled on the device) and same residual target for each precision.
+    max_basis: int or {precision: int} (the FP64 basis must fit HBM at N_s = 18)."""
     import torch
     from paper_1004_3354_amd import ed, workloads as wl
     out = {}
-    v64 = None
     for prec in precs:
+        m = max_basis[prec] if isinstance(max_basis, dict) else max_basis
         phys, nn, b, H, tset = setup(cfg, prec)
-        if v64 is None:
-            v64 = torch.empty(b.D, dtype=torch.float64, device="cuda")
-            ed.fill_random(v64, wl.start_vector_seed(seed_idx), 1)
-        v0 = v64 if prec == ed.ED_FP64 else v64.float()
-        opts = ed.options(tol=tol, max_basis=max_basis)
+        dt = torch.float64 if prec == ed.ED_FP64 else torch.float32
+        v0 = torch.empty(b.D, dtype=dt, device="cuda")
+        ed.fill_random(v0, wl.start_vector_seed(seed_idx), 1)
+        opts = ed.options(tol=tol, max_basis=m)
         ws = torch.empty(H.workspace_bytes(opts, 1), dtype=torch.uint8, device="cuda")
-        x = torch.empty(b.D, dtype=v0.dtype, device="cuda")
-        H.apply(v0, x)                 # tunes the apply schedule outside the timed region
-        del x
+        y = ws[: b.D * v0.element_size()].view(dt)   # scratch: tune the schedule outside the timed region
+        H.apply(v0, y)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         E, info = H.lanczos_ground(v0, opts, ws=ws, allow_noconv=True)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        dt_s = time.perf_counter() - t0
         key = "fp64" if prec == ed.ED_FP64 else "fp32_mixed"
-        out[key] = {"seconds": round(dt, 4), "E0": E, "iters": info["iters"], "restarts": info["restarts"],
-                    "converged": info["converged"], "residual": info["residual"], "setup_s": round(tset, 3)}
-        log("time-to-E0 %s: %.3f s E0=%.12f iters=%d" % (key, dt, E, info["iters"]))
-        del ws, H, b
-        if prec != ed.ED_FP64:
-            del v0
+        out[key] = {"seconds": round(dt_s, 4), "E0": E, "iters": info["iters"], "restarts": info["restarts"],
+                    "converged": info["converged"], "residual": info["residual"], "setup_s": round(tset, 3),
+                    "max_basis": m}
+        log("time-to-E0 %s: %.3f s E0=%.12f iters=%d restarts=%d" % (key, dt_s, E, info["iters"],
+                                                                     info["restarts"]))
+        del ws, y, H, b, v0
         torch.cuda.empty_cache()
-    del v64
-    torch.cuda.empty_cache()
     out["max_basis"] = max_basis
     out["tol"] = tol
     if "fp64" in out and "fp32_mixed" in out:
@@ -165,6 +164,80 @@ def time_to_e0(cfg, precs, max_basis, tol, seed_idx):
     return out
 
 
+def batched_bench():
+    """All 169 sectors of the N_s = 12 three-orbital impurity: one batched FP32-mixed
+    Lanczos (graph-replayed steps) vs the same sectors solved one after another."""
+    import numpy as np
+    import torch
+    from paper_1004_3354_amd import ed, models, workloads as wl
+    phys, sectors = wl.config(3)
+    p = models.params_from_model(phys)
+    t0 = time.perf_counter()
+    hs = [ed.Hamiltonian(p, ed.Basis(phys["Ns"], a, b), ed.ED_FP32) for (a, b) in sectors]
+    torch.cuda.synchronize()
+    tset = time.perf_counter() - t0
+    opts = ed.options(tol=1e-7, max_basis=60)
+    seed = wl.start_vector_seed(3)
+    ed.lanczos_ground_batched(hs, opts, seed=seed)          # graph capture + tile tuning
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E, info = ed.lanczos_ground_batched(hs, opts, seed=seed)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    Dmax = max(h.D for h in hs)
+    ws = torch.empty(max(h.workspace_bytes(opts, 1) for h in hs), dtype=torch.uint8, device="cuda")
+    v0 = torch.empty(Dmax, dtype=torch.float32, device="cuda")
+    for h in hs:                                             # tune every sector's apply schedule
+        ed.fill_random(v0[:h.D], seed, 1)
+        h.apply(v0[:h.D], ws[:4 * h.D].view(torch.float32))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Es = []
+    for i, h in enumerate(hs):
+        ed.fill_random(v0[:h.D], seed + i, 1)
+        e, _ = h.lanczos_ground(v0[:h.D], opts, ws=ws, allow_noconv=True)
+        Es.append(e)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    out = {"workload": "kanamori_Ns12_3orb_9bath_all169_sectors", "sum_D": int(sum(h.D for h in hs)),
+           "batched_s": round(tb, 4), "sequential_s": round(ts, 4), "speedup": round(ts / tb, 2),
+           "setup_s": round(tset, 3), "tile": int(ed._lib.ed_batched_last_tile()),
+           "all_converged": all(i["converged"] for i in info),
+           "max_abs_diff_batched_vs_sequential": float(np.max(np.abs(np.array(E) - np.array(Es))))}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_e0.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))["entries"].get("cfg3")
+        if g:
+            ref = np.array([g["sectors"]["%d,%d" % s]["evals"][0] for s in sectors])
+            out["max_rel_err_vs_oracle"] = float(np.max(np.abs(np.array(E) - ref) / np.maximum(1.0, np.abs(ref))))
+    log("batched 169 sectors: %.3f s (sequential %.3f s)" % (tb, ts))
+    return out
+
+
+def pmc_pass(args):
+    """Workload for rocprofv3 counter runs: the tuned FP32 apply, then plain
+    device copies of x (4 D bytes read, 4 D bytes written) to calibrate the
+    counters against a kernel whose traffic is known."""
+    import torch
+    from paper_1004_3354_amd import ed
+    cfg = 2 if args.workload == "ns15" else 4
+    phys, nn, b, H, _ = setup(cfg, ed.ED_FP32)
+    x = torch.empty(b.D, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    ed.fill_random(x, 12345, 0)
+    H.apply(x, y)
+    torch.cuda.synchronize()
+    log("pmc-pass %s D=%d schedule %s" % (args.workload, b.D, ed.variant_name(H.current_variant())))
+    for _ in range(args.steps):
+        H.apply(x, y)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": args.workload, "D": b.D, "schedule": ed.variant_name(H.current_variant()),
+                      "steps": args.steps, "copy_bytes_each_way": 4 * b.D}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,7 +246,12 @@ def main():
     ap.add_argument("--no-e0", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ns18", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--e0-ns18", action="store_true", help="also time-to-E0 at N_s=18 (minutes)")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="counter runs: tune, then K FP32 applies and K plain copies of x (known bytes)")
+    ap.add_argument("--workload", choices=["ns15", "ns18"], default="ns15",
+                    help="sector used by --pmc-pass")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sector is held by a single MI355X and no multi-GPU "
@@ -182,6 +260,9 @@ def main():
     import torch
     from paper_1004_3354_amd import ed
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.pmc_pass:
+        pmc_pass(args)
+        return
 
     # ---- headline: FP32 H.v on the N_s = 15 sector
     phys, nn, b, H, tset = setup(2, ed.ED_FP32)
@@ -199,7 +280,8 @@ def main():
     achieved = alg_bytes / kern_s / 1e9
     log("FP32 H.v: %.4f ms/step (events %.4f ms), %.1f GB/s, schedule %s" % (ms, kern_s * 1e3, value, variant))
     wl15 = "kanamori_Ns15_3orb_12bath_sector7_7"
-    traffic = traffic_from_profile(wl15)
+    traffic = traffic_from_profile(wl15, variant)
+    variant_id = H.current_variant()
     del x, y, H, b
     torch.cuda.empty_cache()
 
@@ -231,7 +313,10 @@ def main():
             ns18 = {"workload": "kanamori_Ns18_3orb_15bath_sector9_9", "D": b18.D,
                     "ms_per_apply": round(e18 / k18 * 1e3, 4), "gbps": round(g18, 1),
                     "frac": round(g18 / HBM_PEAK_GBS, 4), "setup_s": round(t18, 3),
-                    "schedule": ed.variant_name(H18.current_variant())}
+                    "schedule": ed.variant_name(H18.current_variant()),
+                    "schedule_id": H18.current_variant(),
+                    "traffic": traffic_from_profile("kanamori_Ns18_3orb_15bath_sector9_9",
+                                                    ed.variant_name(H18.current_variant()))}
             log("N_s=18 FP32 H.v: %.3f ms, %.1f GB/s" % (e18 / k18 * 1e3, g18))
             del x, y, H18, b18
             torch.cuda.empty_cache()
@@ -239,11 +324,13 @@ def main():
     # ---- time to E0, FP32-mixed vs FP64, same start vector and target
     e0 = None
     if not args.no_e0:
-        e0 = time_to_e0(2, [ed.ED_FP32, ed.ED_FP64], max_basis=100, tol=1e-7, seed_idx=2)
+        e0 = time_to_e0(2, [ed.ED_FP32, ed.ED_FP64], max_basis=150, tol=1e-7, seed_idx=2)
     e0_18 = None
     if args.e0_ns18:
-        e0_18 = time_to_e0(4, [ed.ED_FP32, ed.ED_FP64], max_basis=20, tol=1e-7, seed_idx=4)
+        e0_18 = time_to_e0(4, [ed.ED_FP32, ed.ED_FP64], max_basis={ed.ED_FP32: 24, ed.ED_FP64: 11},
+                           tol=1e-7, seed_idx=4)
 
+    batched = None if args.no_batched else batched_bench()
     cpu = None if args.no_cpu else cpu_baseline(2)
     if cpu:
         log("cpu baseline: %s" % cpu)
@@ -254,7 +341,8 @@ def main():
         "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp32", "data": "synthetic (seeded baths and SplitMix64 vectors)",
         "config": {"workload": wl15, "Ns": 15, "sector": list(nn), "D": D,
-                   "step": "one FP32 matrix-free H.v (x, y resident in HBM)", "schedule": variant},
+                   "step": "one FP32 matrix-free H.v (x, y resident in HBM)", "schedule": variant,
+                   "schedule_id": variant_id},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_apply<float,float> (%s)" % variant,
@@ -265,6 +353,7 @@ def main():
         "ns18_hv_fp32": ns18,
         "time_to_e0_ns15": e0,
         "time_to_e0_ns18": e0_18,
+        "batched_ns12": batched,
     }
     print(json.dumps(rec), flush=True)
 

@@ -220,7 +220,9 @@ ed_status ed_lanczos_ground(ed_ham_t h, const ed_lanczos_opts *opts, const void 
  * evals[k]; optional DEVICE evecs[k][D].  Each eigenpair is found by a restarted
  * Lanczos run on H restricted to the orthogonal complement of the pairs already
  * locked (explicit deflation), which also recovers every copy of a degenerate
- * eigenvalue.  info[k] (HOST, may be NULL) per eigenpair. */
+ * eigenvalue: the first run starts from v0, every later one from a fresh
+ * pseudo-random vector (SplitMix64 normal stream 0x5EED0000 + index), because
+ * one start vector's Krylov space holds a single vector per distinct eigenvalue.  info[k] (HOST, may be NULL) per eigenpair. */
 ed_status ed_arnoldi_lowest(ed_ham_t h, int k, const ed_lanczos_opts *opts, const void *v0,
                             void *ws, size_t ws_bytes, double *evals, void *evecs,
                             ed_info *info, void *stream);

@@ -74,91 +74,116 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return s;
 }
 
-// MODE 0: y = H x.  MODE 1: partials of <x,Hx> and <x,x>.  MODE 2: partials of
-// ||Hx - theta x||^2.  TX = storage type of x and y, TA = arithmetic type.
-template <typename TX, typename TA, int R, int BS, bool LDS, int MODE>
+// Row-window kernel.  A workgroup owns R consecutive rows and one window
+// [w0, w0 + wl) of down ranks (a run of states sharing their top bits, so most
+// down-spin hops stay inside it); the R x wl block of x is staged in LDS.  Each
+// thread owns one column at a time and keeps R accumulators, so every hop
+// table entry is loaded once per R output elements.
+// UPX = true: full product (diagonal, 1 (x) H_dn, H_up (x) 1, four-fermion terms).
+// UPX = false: row-local part only (diagonal and 1 (x) H_dn), the first pass of
+// the two-pass schedule.  MODE 0 stores y; MODE 1 / 2 write per-workgroup
+// partials of <x,Hx>, <x,x> / ||Hx - theta x||^2 instead.
+template <typename TX, typename TA, int R, int BS, int MODE, bool UPX>
 __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[2][BS / 64];
     TX *xs = reinterpret_cast<TX *>(smem_raw);
 
     const int64_t ddn = a.ddn;
+    const int nwin = a.nwin;
     const int64_t G = (a.dup + R - 1) / R;
-    const int64_t g = xcd_remap(blockIdx.x, G);
+    const int64_t t = xcd_remap(blockIdx.x, G * nwin);
+    const int64_t g = t / nwin;
+    const int wi = (int)(t - g * nwin);
     const int64_t u0 = g * R;
     const int nr = (int)((a.dup - u0) < R ? (a.dup - u0) : R);
+    const int32_t w0 = a.win[wi].x, wl = a.win[wi].y;
 
-    const TX *xrow[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) xrow[r] = a.x + (u0 + (r < nr ? r : 0)) * ddn;
-
-    if constexpr (LDS) {
-        for (int r = 0; r < nr; ++r)
-            for (int64_t d = threadIdx.x; d < ddn; d += BS) xs[r * ddn + d] = xrow[r][d];
-        __syncthreads();
+    for (int r = 0; r < nr; ++r) {
+        const TX *src = a.x + (u0 + r) * ddn + w0;
+        for (int k = threadIdx.x; k < wl; k += BS) xs[r * wl + k] = src[k];
     }
+    __syncthreads();
 
     TA eu[R];
     uint32_t su[R], cu[R];
-    int32_t hb[R], he[R];
+    int32_t hb[R], he[R], xb[R], xe[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (r < nr) {
-            eu[r] = a.up_e[u0 + r];
-            su[r] = a.up_st[u0 + r];
-            cu[r] = a.up_c[u0 + r];
-            hb[r] = a.up_off[u0 + r];
-            he[r] = a.up_off[u0 + r + 1];
-        } else {
-            eu[r] = (TA)0;
-            su[r] = 0u;
-            cu[r] = 0u;
-            hb[r] = 0;
-            he[r] = 0;
-        }
+        const bool ok = r < nr;
+        const int64_t u = u0 + (ok ? r : 0);
+        eu[r] = ok ? a.up_e[u] : (TA)0;
+        su[r] = ok ? a.up_st[u] : 0u;
+        cu[r] = ok ? a.up_c[u] : 0u;
+        hb[r] = ok ? a.up_off[u] : 0;
+        he[r] = ok ? a.up_off[u + 1] : 0;
+        xb[r] = ok ? a.xl_off[u] : 0;
+        xe[r] = ok ? a.xl_off[u + 1] : 0;
     }
 
     double p0 = 0.0, p1 = 0.0;
     const int lane = threadIdx.x & 63;
-    for (int64_t d = threadIdx.x; d < ddn; d += BS) {
+    const int64_t dend = (int64_t)w0 + wl;
+    for (int64_t d0 = (int64_t)(w0 & ~63); d0 < dend; d0 += BS) {
+        const int64_t d = d0 + threadIdx.x;
+        if (d < w0 || d >= dend) continue;
+        const int32_t ld = (int32_t)(d - w0);
         const int64_t sl = d >> 6;
         const int32_t eb = a.dn_ell_off[sl], ee = a.dn_ell_off[sl + 1];
         const TA edn = a.dn_e[d];
         const uint32_t sd = a.dn_st[d];
         const uint32_t cd = a.dn_c[d];
         TA acc[R];
-        TA xv[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            xv[r] = LDS ? (TA)xs[r * ddn + d] : (TA)xrow[r][d];
-            acc[r] = (eu[r] + edn + cross_term(a, su[r], sd, cu[r], cd)) * xv[r];
-        }
-        // 1 (x) H_dn: gathers within the row
-        for (int32_t e = eb + lane; e < ee; e += 64) {
-            const int32_t t = a.dn_ell_tgt[e];
-            const TA s = a.dn_ell_sa[e];
+        for (int r = 0; r < R; ++r)
+            acc[r] = (eu[r] + edn + cross_term(a, su[r], sd, cu[r], cd)) * (TA)xs[r * wl + ld];
+        // 1 (x) H_dn: four table entries in flight; targets inside the window
+        // come from LDS, the rest from memory
+        for (int32_t e = eb + lane; e < ee; e += 256) {
+            int32_t tt[4];
+            TA ss[4];
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += s * (LDS ? (TA)xs[r * ddn + t] : (TA)xrow[r][t]);
-        }
-        // H_up (x) 1: whole partner rows, coalesced along d
+            for (int k = 0; k < 4; ++k) {
+                const bool ok = e + 64 * k < ee;
+                tt[k] = ok ? a.dn_ell_tgt[e + 64 * k] : (int32_t)d;
+                ss[k] = ok ? a.dn_ell_sa[e + 64 * k] : (TA)0;
+            }
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            for (int32_t e = hb[r]; e < he[r]; ++e) {
-                const int64_t src = a.up_tgt[e];
-                acc[r] += a.up_sa[e] * (TA)a.x[src * ddn + d];
+            for (int k = 0; k < 4; ++k) {
+                const int32_t l = tt[k] - w0;
+                if ((uint32_t)l < (uint32_t)wl) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] += ss[k] * (TA)xs[r * wl + l];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        acc[r] += ss[k] * (TA)a.x[(u0 + (r < nr ? r : 0)) * ddn + tt[k]];
+                }
             }
         }
-        // four-fermion terms: products of an up move and a down move
-        for (int q = 0; q < a.nx; ++q) {
-            const XTermDev<TA> xt = a.xt[q];
-            const int32_t md = a.dn_mv[(int64_t)xt.dn_mv * ddn + d];
+        if constexpr (UPX) {
+            // H_up (x) 1: partner rows, coalesced along d
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (r >= nr) break;
-                const int32_t mu = a.up_mv[(int64_t)xt.up_mv * a.dup + u0 + r];
-                if (mu >= 0 && md >= 0) {
-                    TA v = xt.amp * (TA)a.x[(int64_t)(mu >> 1) * ddn + (md >> 1)];
-                    acc[r] += ((mu ^ md) & 1) ? -v : v;
+                int32_t e = hb[r];
+                for (; e + 4 <= he[r]; e += 4) {
+                    const TA v0 = (TA)a.x[(int64_t)a.up_tgt[e] * ddn + d];
+                    const TA v1 = (TA)a.x[(int64_t)a.up_tgt[e + 1] * ddn + d];
+                    const TA v2 = (TA)a.x[(int64_t)a.up_tgt[e + 2] * ddn + d];
+                    const TA v3 = (TA)a.x[(int64_t)a.up_tgt[e + 3] * ddn + d];
+                    acc[r] += a.up_sa[e] * v0 + a.up_sa[e + 1] * v1 + a.up_sa[e + 2] * v2 + a.up_sa[e + 3] * v3;
+                }
+                for (; e < he[r]; ++e) acc[r] += a.up_sa[e] * (TA)a.x[(int64_t)a.up_tgt[e] * ddn + d];
+            }
+            // four-fermion terms allowed on each row: per-row list, branch-free gathers
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                for (int32_t e = xb[r]; e < xe[r]; ++e) {
+                    const int32_t m = a.dn_mv[(int64_t)a.xl_tab[e] * ddn + d];
+                    const int64_t c = m >= 0 ? (int64_t)(m >> 1) : d;
+                    TA v = (TA)a.x[(int64_t)a.xl_src[e] * ddn + c];
+                    v = m >= 0 ? ((m & 1) ? -v : v) : (TA)0;
+                    acc[r] += a.xl_amp[e] * v;
                 }
             }
         }
@@ -168,10 +193,11 @@ __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
             if constexpr (MODE == 0) {
                 a.y[(u0 + r) * ddn + d] = (TX)acc[r];
             } else if constexpr (MODE == 1) {
-                p0 += (double)xv[r] * (double)acc[r];
-                p1 += (double)xv[r] * (double)xv[r];
+                const double xv = (double)xs[r * wl + ld];
+                p0 += xv * (double)acc[r];
+                p1 += xv * xv;
             } else {
-                const double df = (double)acc[r] - a.theta * (double)xv[r];
+                const double df = (double)acc[r] - a.theta * (double)xs[r * wl + ld];
                 p0 += df * df;
             }
         }
@@ -186,18 +212,135 @@ __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
     }
 }
 
+// Second pass of the two-pass schedule: y += (H_up (x) 1) x + four-fermion
+// terms over column bands.  Blocks run band-major, so while one band is in
+// flight its slice of x (D_up x band) stays in the last-level cache and each
+// partner row segment is fetched from HBM about once instead of once per
+// neighbouring row.  A thread owns one column of RB rows at a time.
+template <typename TX, typename TA, int RB, int BS>
+__global__ __launch_bounds__(BS) void k_apply_band(ApplyArgs<TX, TA> a, int64_t band) {
+    const int64_t ddn = a.ddn;
+    const int64_t G = (a.dup + RB - 1) / RB;
+    const int64_t bi = blockIdx.x / G;
+    const int64_t g = blockIdx.x - bi * G;
+    const int64_t u0 = g * RB;
+    const int nr = (int)((a.dup - u0) < RB ? (a.dup - u0) : RB);
+    const int64_t c0 = bi * band, c1 = (c0 + band < ddn) ? c0 + band : ddn;
+    int32_t hb[RB], he[RB], xb[RB], xe[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const bool ok = r < nr;
+        const int64_t u = u0 + (ok ? r : 0);
+        hb[r] = ok ? a.up_off[u] : 0;
+        he[r] = ok ? a.up_off[u + 1] : 0;
+        xb[r] = ok ? a.xl_off[u] : 0;
+        xe[r] = ok ? a.xl_off[u + 1] : 0;
+    }
+    for (int64_t d = c0 + threadIdx.x; d < c1; d += BS) {
+        TA acc[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[r] = r < nr ? (TA)a.y[(u0 + r) * ddn + d] : (TA)0;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            int32_t e = hb[r];
+            for (; e + 4 <= he[r]; e += 4) {
+                const TA v0 = (TA)a.x[(int64_t)a.up_tgt[e] * ddn + d];
+                const TA v1 = (TA)a.x[(int64_t)a.up_tgt[e + 1] * ddn + d];
+                const TA v2 = (TA)a.x[(int64_t)a.up_tgt[e + 2] * ddn + d];
+                const TA v3 = (TA)a.x[(int64_t)a.up_tgt[e + 3] * ddn + d];
+                acc[r] += a.up_sa[e] * v0 + a.up_sa[e + 1] * v1 + a.up_sa[e + 2] * v2 + a.up_sa[e + 3] * v3;
+            }
+            for (; e < he[r]; ++e) acc[r] += a.up_sa[e] * (TA)a.x[(int64_t)a.up_tgt[e] * ddn + d];
+            for (int32_t q = xb[r]; q < xe[r]; ++q) {
+                const int32_t m = a.dn_mv[(int64_t)a.xl_tab[q] * ddn + d];
+                const int64_t c = m >= 0 ? (int64_t)(m >> 1) : d;
+                TA v = (TA)a.x[(int64_t)a.xl_src[q] * ddn + c];
+                v = m >= 0 ? ((m & 1) ? -v : v) : (TA)0;
+                acc[r] += a.xl_amp[q] * v;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (r < nr) a.y[(u0 + r) * ddn + d] = (TX)acc[r];
+    }
+}
+
 // ---------------------------------------------------------- variant table --
+// kind 0: single pass.  kind 1: two passes (row-local, then banded up spin).
 struct Variant {
-    int R, BS;
-    bool lds;
+    int kind, R, BS;
+    int64_t band;
     const char *name;
 };
 static const Variant kVariants[] = {
-    {1, 256, true, "lds_r1_b256"},  {2, 256, true, "lds_r2_b256"},  {2, 512, true, "lds_r2_b512"},
-    {4, 512, true, "lds_r4_b512"},  {1, 256, false, "gl_r1_b256"},  {2, 256, false, "gl_r2_b256"},
-    {4, 256, false, "gl_r4_b256"},
+    {0, 1, 256, 0, "rw_r1_b256"},          {0, 2, 256, 0, "rw_r2_b256"},
+    {0, 4, 256, 0, "rw_r4_b256"},          {0, 8, 256, 0, "rw_r8_b256"},
+    {0, 16, 256, 0, "rw_r16_b256"},        {0, 8, 512, 0, "rw_r8_b512"},
+    {1, 8, 256, 512, "tp_r8_band512"},     {1, 8, 256, 2048, "tp_r8_band2048"},
+    {1, 16, 256, 512, "tp_r16_band512"},   {1, 16, 256, 2048, "tp_r16_band2048"},
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+static constexpr int64_t kDynBudget = 163840 - 8192;  // LDS left for the staged x block
+
+// Windows of down ranks staged per workgroup: the whole row if it fits, else
+// runs of states that share their top t bits (contiguous in rank order; a hop
+// that does not touch those bits stays inside), merged greedily up to `cap`.
+static std::vector<int2> plan_windows(const std::vector<uint32_t> &st, int ns, int64_t cap) {
+    const int64_t n = (int64_t)st.size();
+    std::vector<int2> w;
+    if (n <= cap) {
+        w.push_back(make_int2(0, (int)n));
+        return w;
+    }
+    for (int t = 1; t <= ns; ++t) {
+        const int sh = ns - t;
+        std::vector<std::pair<int64_t, int64_t>> runs;
+        int64_t a = 0;
+        for (int64_t i = 1; i <= n; ++i)
+            if (i == n || (st[i] >> sh) != (st[i - 1] >> sh)) {
+                runs.push_back({a, i - a});
+                a = i;
+            }
+        bool ok = true;
+        for (auto &r : runs)
+            if (r.second > cap) ok = false;
+        if (!ok) continue;
+        int64_t cs = runs[0].first, cl = 0;
+        for (auto &r : runs) {
+            if (cl + r.second > cap) {
+                w.push_back(make_int2((int)cs, (int)cl));
+                cs = r.first;
+                cl = 0;
+            }
+            cl += r.second;
+        }
+        w.push_back(make_int2((int)cs, (int)cl));
+        return w;
+    }
+    for (int64_t a = 0; a < n; a += cap) w.push_back(make_int2((int)a, (int)std::min(cap, n - a)));
+    return w;
+}
+
+static const int2 *windows_for(ed_ham_s *h, int64_t cap, int *nwin, int *wmax) {
+    for (size_t i = 0; i < h->windows.size(); ++i)
+        if (h->windows[i].first == cap) {
+            *nwin = h->window_counts[2 * i];
+            *wmax = h->window_counts[2 * i + 1];
+            return h->windows[i].second->as<int2>();
+        }
+    std::vector<int2> w = plan_windows(h->dn_states_host, h->ns, cap);
+    int mx = 0;
+    for (auto &v : w) mx = std::max(mx, v.y);
+    DevMem *m = new DevMem();
+    m->alloc(w.size() * sizeof(int2));
+    ED_HIP(hipMemcpy(m->p, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice));
+    h->windows.push_back({cap, m});
+    h->window_counts.push_back((int)w.size());
+    h->window_counts.push_back(mx);
+    *nwin = (int)w.size();
+    *wmax = mx;
+    return m->as<int2>();
+}
 
 template <typename TX, typename TA>
 static ApplyArgs<TX, TA> make_args(const ed_ham_s *h, const void *x, void *y, double *partials, double theta);
@@ -233,6 +376,10 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.xtab = h->xtab64.as<double>();
     a.nx = h->nx;
     a.xt = h->xt64.as<XTermDev<double>>();
+    a.xl_off = h->xl_off.as<int32_t>();
+    a.xl_src = h->xl_src.as<int32_t>();
+    a.xl_tab = h->xl_tab.as<int32_t>();
+    a.xl_amp = h->xl_amp64.as<double>();
     a.partials = partials;
     a.theta = theta;
     return a;
@@ -269,6 +416,10 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.xtab = h->xtab32.as<float>();
     a.nx = h->nx;
     a.xt = h->xt32.as<XTermDev<float>>();
+    a.xl_off = h->xl_off.as<int32_t>();
+    a.xl_src = h->xl_src.as<int32_t>();
+    a.xl_tab = h->xl_tab.as<int32_t>();
+    a.xl_amp = h->xl_amp32.as<float>();
     a.partials = partials;
     a.theta = theta;
     return a;
@@ -286,42 +437,62 @@ ApplyArgs<float, double> make_args<float, double>(const ed_ham_s *h, const void 
     return a;
 }
 
-template <typename TX, typename TA, int R, int BS, bool LDS, int MODE>
-static void launch_one(const ApplyArgs<TX, TA> &a, int64_t G, hipStream_t s) {
-    const size_t shm = LDS ? (size_t)R * (size_t)a.ddn * sizeof(TX) : 0;
-    auto kern = k_apply<TX, TA, R, BS, LDS, MODE>;
-    if (LDS) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
-            (void)hipGetLastError();
-            attr_set = true;
-        }
+template <class K>
+static void allow_lds(K kern) {
+    static bool done = false;
+    if (!done) {
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 163840 - 8192);
+        (void)hipGetLastError();
+        done = true;
     }
-    kern<<<(unsigned)G, BS, shm, s>>>(a);
+}
+
+template <typename TX, typename TA, int R, int BS, int MODE, bool UPX>
+static int64_t launch_rw(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s) {
+    int nwin = 0, wmax = 0;
+    a.win = windows_for(h, kDynBudget / (int64_t)(R * sizeof(TX)), &nwin, &wmax);
+    a.nwin = nwin;
+    const int64_t G = (a.dup + R - 1) / R;
+    const size_t shm = (size_t)R * (size_t)wmax * sizeof(TX);
+    auto kern = k_apply<TX, TA, R, BS, MODE, UPX>;
+    allow_lds(kern);
+    kern<<<(unsigned)(G * nwin), BS, shm, s>>>(a);
+    ED_LAUNCH_CHECK();
+    return G * nwin;
+}
+
+template <typename TX, typename TA>
+static void launch_band(const ApplyArgs<TX, TA> &a, int64_t band, hipStream_t s) {
+    constexpr int RB = 8;
+    const int64_t G = (a.dup + RB - 1) / RB;
+    const int64_t nb = (a.ddn + band - 1) / band;
+    k_apply_band<TX, TA, RB, 256><<<(unsigned)(G * nb), 256, 0, s>>>(a, band);
     ED_LAUNCH_CHECK();
 }
 
-template <typename TX, typename TA, int MODE>
-static void launch_variant(const ApplyArgs<TX, TA> &a, int v, hipStream_t s) {
+template <typename TX, typename TA>
+static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipStream_t s) {
     const Variant &V = kVariants[v];
-    const int64_t G = (a.dup + V.R - 1) / V.R;
     switch (v) {
-        case 0: launch_one<TX, TA, 1, 256, true, MODE>(a, G, s); break;
-        case 1: launch_one<TX, TA, 2, 256, true, MODE>(a, G, s); break;
-        case 2: launch_one<TX, TA, 2, 512, true, MODE>(a, G, s); break;
-        case 3: launch_one<TX, TA, 4, 512, true, MODE>(a, G, s); break;
-        case 4: launch_one<TX, TA, 1, 256, false, MODE>(a, G, s); break;
-        case 5: launch_one<TX, TA, 2, 256, false, MODE>(a, G, s); break;
-        case 6: launch_one<TX, TA, 4, 256, false, MODE>(a, G, s); break;
+        case 0: launch_rw<TX, TA, 1, 256, 0, true>(h, a, s); break;
+        case 1: launch_rw<TX, TA, 2, 256, 0, true>(h, a, s); break;
+        case 2: launch_rw<TX, TA, 4, 256, 0, true>(h, a, s); break;
+        case 3: launch_rw<TX, TA, 8, 256, 0, true>(h, a, s); break;
+        case 4: launch_rw<TX, TA, 16, 256, 0, true>(h, a, s); break;
+        case 5: launch_rw<TX, TA, 8, 512, 0, true>(h, a, s); break;
+        case 6:
+        case 7: launch_rw<TX, TA, 8, 256, 0, false>(h, a, s); launch_band(a, V.band, s); break;
+        case 8:
+        case 9: launch_rw<TX, TA, 16, 256, 0, false>(h, a, s); launch_band(a, V.band, s); break;
         default: fail(ED_EINVAL, "bad apply variant %d", v);
     }
 }
 
 static bool variant_fits(const ed_ham_s *h, int v, size_t elem) {
+    if (v < 0 || v >= kNumVariants) return false;
     const Variant &V = kVariants[v];
-    if (!V.lds) return true;
-    return (size_t)V.R * (size_t)h->ddn * elem <= (size_t)kLdsBudget;
+    if (V.kind == 1 && h->nx == 0 && h->sp[0].nnz == 0) return false;  // nothing for the second pass
+    return true;
 }
 
 int apply_variant_count(const ed_ham_s *) { return kNumVariants; }
@@ -332,15 +503,15 @@ const char *apply_variant_name(const ed_ham_s *, int v) {
 
 static void launch_store(ed_ham_s *h, int v, const void *x, void *y, hipStream_t s) {
     if (h->prec == ED_FP64)
-        launch_variant<double, double, 0>(make_args<double, double>(h, x, y, nullptr, 0.0), v, s);
+        launch_variant<double, double>(h, make_args<double, double>(h, x, y, nullptr, 0.0), v, s);
     else
-        launch_variant<float, float, 0>(make_args<float, float>(h, x, y, nullptr, 0.0), v, s);
+        launch_variant<float, float>(h, make_args<float, float>(h, x, y, nullptr, 0.0), v, s);
 }
 
 void apply_launch_variant(ed_ham_s *h, int v, const void *x, void *y, hipStream_t s) {
     if (v < 0 || v >= kNumVariants) fail(ED_EINVAL, "apply variant %d out of range", v);
     const size_t elem = h->prec == ED_FP64 ? 8 : 4;
-    if (!variant_fits(h, v, elem)) fail(ED_EINVAL, "apply variant %s needs more LDS than a workgroup has", kVariants[v].name);
+    if (!variant_fits(h, v, elem)) fail(ED_EINVAL, "apply variant %s does not apply to this Hamiltonian", kVariants[v].name);
     launch_store(h, v, x, y, s);
 }
 
@@ -417,23 +588,24 @@ void ensure_redbuf(ed_ham_s *h, size_t doubles) {
 
 template <typename TX>
 static void rayleigh_impl(ed_ham_s *h, const void *x, double *rq, double *resid, hipStream_t s) {
-    // R = 1 global-gather schedule: valid for every sector size
-    const int64_t G = h->dup;
-    ensure_redbuf(h, (size_t)2 * G + 8);
+    int nwin = 0, wmax = 0;
+    (void)windows_for(h, kDynBudget / (int64_t)sizeof(TX), &nwin, &wmax);
+    const int64_t nb = h->dup * (int64_t)nwin;
+    ensure_redbuf(h, (size_t)2 * nb + 8);
     double *part = h->redbuf.as<double>();
-    double *out = part + 2 * G;
+    double *out = part + 2 * nb;
     double hv[2];
     ApplyArgs<TX, double> a = make_args<TX, double>(h, x, nullptr, part, 0.0);
-    launch_one<TX, double, 1, 256, false, 1>(a, G, s);
-    k_sum_pairs<<<1, 256, 0, s>>>(part, G, out);
+    launch_rw<TX, double, 1, 512, 1, true>(h, a, s);
+    k_sum_pairs<<<1, 256, 0, s>>>(part, nb, out);
     ED_LAUNCH_CHECK();
     ED_HIP(hipMemcpyAsync(hv, out, sizeof(hv), hipMemcpyDeviceToHost, s));
     ED_HIP(hipStreamSynchronize(s));
     if (!(hv[1] > 0.0)) fail(ED_EINVAL, "ed_rayleigh: zero vector");
     const double theta = hv[0] / hv[1];
     a.theta = theta;
-    launch_one<TX, double, 1, 256, false, 2>(a, G, s);
-    k_sum_pairs<<<1, 256, 0, s>>>(part, G, out);
+    launch_rw<TX, double, 1, 512, 2, true>(h, a, s);
+    k_sum_pairs<<<1, 256, 0, s>>>(part, nb, out);
     ED_LAUNCH_CHECK();
     double r2[2];
     ED_HIP(hipMemcpyAsync(r2, out, sizeof(r2), hipMemcpyDeviceToHost, s));

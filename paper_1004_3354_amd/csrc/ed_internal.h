@@ -173,9 +173,18 @@ struct ed_ham_s {
     int nx = 0;
     std::vector<ed::XTerm> xterms;
     ed::DevMem xt64, xt32;      // XTermDev<double>/<float> [nx]
+    // per up state: the four-fermion terms whose up move is allowed, as CSR
+    // (source up rank, down move table, signed amplitude)
+    ed::DevMem xl_off, xl_src, xl_tab, xl_amp64, xl_amp32;
     ed::ApplyPlan plan;
     ed::DevMem redbuf;          // small FP64 reduction scratch owned by the handle
     size_t redbuf_doubles = 0;
+    std::vector<uint32_t> dn_states_host;           // for the LDS window plan
+    std::vector<std::pair<int64_t, ed::DevMem *>> windows;  // (capacity, device int2 list)
+    std::vector<int> window_counts;
+    ~ed_ham_s() {
+        for (auto &w : windows) delete w.second;
+    }
 };
 
 namespace ed {
@@ -208,9 +217,14 @@ struct ApplyArgs {
     // four-fermion terms
     int nx;
     const XTermDev<TA> *xt;
+    const int32_t *xl_off, *xl_src, *xl_tab;
+    const TA *xl_amp;
     // reductions (Rayleigh quotient / residual epilogues)
     double *partials;
     double theta;
+    // down-spin windows staged in LDS: (first rank, length) per window
+    const int2 *win;
+    int nwin;
 };
 
 // Build all tables of a Hamiltonian handle (tables.hip).

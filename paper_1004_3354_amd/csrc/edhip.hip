@@ -3,6 +3,6 @@
 #include "basis.hip"
 #include "tables.hip"
 #include "apply.hip"
-#include "lanczos.hip"
 #include "fill.hip"
+#include "lanczos.hip"
 #include "batched.hip"

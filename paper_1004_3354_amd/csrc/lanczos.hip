@@ -480,10 +480,17 @@ struct Solver {
 
     // One eigenpair by restarted Lanczos.  `out` receives the Ritz vector
     // normalised to 1 (it must not be one of the slots).  Returns the status.
-    ed_status run(const void *v0, void *out, double *E, ed_info *info) {
+    // fresh >= 0: start from the SplitMix64 normal stream `fresh` instead of v0.
+    ed_status run(const void *v0, void *out, double *E, ed_info *info, int64_t fresh = -1) {
         const int m = w.m;
         ed_info inf{};
-        ED_HIP(hipMemcpyAsync(w.slots[0], v0, (size_t)h->D * w.elem, hipMemcpyDeviceToDevice, s));
+        if (fresh >= 0) {
+            k_fill<<<grid_for(h->D, 256, 1 << 16), 256, 0, s>>>(w.slots[0], h->D, (uint64_t)fresh, 1,
+                                                               h->prec == ED_FP32 ? 1 : 0);
+            ED_LAUNCH_CHECK();
+        } else {
+            ED_HIP(hipMemcpyAsync(w.slots[0], v0, (size_t)h->D * w.elem, hipMemcpyDeviceToDevice, s));
+        }
         std::vector<void *> kr(w.slots.begin(), w.slots.end());
         upload_pointers(kr);
         prepare_start(kr[0]);
@@ -641,7 +648,11 @@ static ed_status solve(ed_ham_t h, int k, const ed_lanczos_opts *opts, const voi
         for (int e = 0; e < k; ++e) {
             double E = 0.0;
             ed_info inf{};
-            const ed_status r = sv.run(v0, sv.w.locked[e], &E, &inf);
+            // A Krylov space built from one start vector holds a single vector per
+            // distinct eigenvalue, so after deflating one copy of a repeated
+            // eigenvalue the same start vector has no component left on the other
+            // copies: every further eigenpair starts from a fresh random vector.
+            const ed_status r = sv.run(v0, sv.w.locked[e], &E, &inf, e == 0 ? -1 : (int64_t)(0x5EED0000ull + e));
             if (r != ED_OK) result = r;
             evals[e] = E;
             if (info) info[e] = inf;

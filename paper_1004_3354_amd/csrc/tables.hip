@@ -193,6 +193,37 @@ __global__ void k_move(const uint32_t *st, int64_t dim, int ns, int n, int src, 
     }
 }
 
+// per up state u: the terms q whose up move applies to u, with the source rank
+// and the signed amplitude folded together
+__global__ void k_xlist_count(const int32_t *up_mv, int64_t dup, const XTermDev<double> *xt, int nx,
+                              int64_t *cnt) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < dup; u += (int64_t)gridDim.x * blockDim.x) {
+        int c = 0;
+        for (int q = 0; q < nx; ++q) c += up_mv[(int64_t)xt[q].up_mv * dup + u] >= 0;
+        cnt[u] = c;
+    }
+}
+
+__global__ void k_xlist_fill(const int32_t *up_mv, int64_t dup, const XTermDev<double> *xt, int nx,
+                             const int64_t *off64, int32_t *off, int32_t *src, int32_t *tab, double *a64,
+                             float *a32) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < dup; u += (int64_t)gridDim.x * blockDim.x) {
+        int64_t e = off64[u];
+        off[u] = (int32_t)e;
+        if (u == dup - 1) off[dup] = (int32_t)off64[dup];
+        for (int q = 0; q < nx; ++q) {
+            const int32_t mu = up_mv[(int64_t)xt[q].up_mv * dup + u];
+            if (mu < 0) continue;
+            const double a = (mu & 1) ? -xt[q].amp : xt[q].amp;
+            src[e] = mu >> 1;
+            tab[e] = xt[q].dn_mv;
+            a64[e] = a;
+            a32[e] = (float)a;
+            ++e;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host ----
 static bool finite_all(const double *a, size_t n) {
     for (size_t i = 0; i < n; ++i)
@@ -409,6 +440,28 @@ static void build_xterms(ed_ham_s *h, const ed_params *p) {
     }
     upload(h->xt64, x64);
     upload(h->xt32, x32);
+    // per-up-state lists
+    const int64_t dup = h->sp[0].dim;
+    DevMem cnt, off64;
+    cnt.alloc((size_t)dup * sizeof(int64_t));
+    off64.alloc((size_t)(dup + 1) * sizeof(int64_t));
+    k_xlist_count<<<grid_for(dup, 256, 1 << 16), 256>>>(h->sp[0].mv.as<int32_t>(), dup, h->xt64.as<XTermDev<double>>(),
+                                                       h->nx, cnt.as<int64_t>());
+    ED_LAUNCH_CHECK();
+    k_scan_i64<<<1, 1024>>>(cnt.as<int64_t>(), off64.as<int64_t>(), dup);
+    ED_LAUNCH_CHECK();
+    int64_t nl = 0;
+    ED_HIP(hipMemcpy(&nl, off64.as<int64_t>() + dup, sizeof(int64_t), hipMemcpyDeviceToHost));
+    h->xl_off.alloc((size_t)(dup + 1) * sizeof(int32_t));
+    h->xl_src.alloc((size_t)std::max<int64_t>(nl, 1) * sizeof(int32_t));
+    h->xl_tab.alloc((size_t)std::max<int64_t>(nl, 1) * sizeof(int32_t));
+    h->xl_amp64.alloc((size_t)std::max<int64_t>(nl, 1) * sizeof(double));
+    h->xl_amp32.alloc((size_t)std::max<int64_t>(nl, 1) * sizeof(float));
+    k_xlist_fill<<<grid_for(dup, 256, 1 << 16), 256>>>(h->sp[0].mv.as<int32_t>(), dup, h->xt64.as<XTermDev<double>>(),
+                                                      h->nx, off64.as<int64_t>(), h->xl_off.as<int32_t>(),
+                                                      h->xl_src.as<int32_t>(), h->xl_tab.as<int32_t>(),
+                                                      h->xl_amp64.as<double>(), h->xl_amp32.as<float>());
+    ED_LAUNCH_CHECK();
     ED_HIP(hipDeviceSynchronize());
 }
 
@@ -465,6 +518,10 @@ void build_tables(ed_ham_s *h, const ed_params *p, const BasisData &b) {
     for (int s = 0; s < 2; ++s) build_spin(h, s, b, p);
     build_cross(h, p);
     build_xterms(h, p);
+    if (h->nx > 64) fail(ED_EUNSUPPORTED, "%d distinct four-fermion terms (at most 64 supported)", h->nx);
+    h->dn_states_host.resize((size_t)h->ddn);
+    ED_HIP(hipMemcpy(h->dn_states_host.data(), h->sp[1].states.p, (size_t)h->ddn * sizeof(uint32_t),
+                     hipMemcpyDeviceToHost));
 }
 
 }  // namespace ed

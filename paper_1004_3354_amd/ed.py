@@ -100,6 +100,7 @@ if hasattr(_lib, "ed_lanczos_ground_batched"):
                                                       ctypes.POINTER(ctypes.c_size_t)])
     _sig("ed_lanczos_ground_batched", ctypes.c_int, [ctypes.c_int, _p, ctypes.POINTER(ed_lanczos_opts), _p,
                                                      ctypes.c_uint64, _p, ctypes.c_size_t, _p, _p, _p])
+    _sig("ed_batched_last_tile", ctypes.c_int64, [])
 
 
 def _check(st: int, ok=(ED_OK,)):

@@ -31,6 +31,10 @@ SMALL = [
     ("kan9_jpoff", wl.kanamori(3, 2, 2.3, 0.4, seed=3, jprime=False), (4, 4)),
     ("kan12_66", wl.config(3)[0], (6, 6)),
     ("kan12_57", wl.config(3)[0], (5, 7)),
+    # wide down-spin rows: several LDS windows per row (top-bit runs)
+    ("hub4x4_1_8", wl.hubbard(4, 4, 1.0, 4.0), (1, 8)),
+    ("hub4x4_2_7", wl.hubbard(4, 4, 1.0, 4.0), (2, 7)),
+    ("kan18_1_9", wl.config(4)[0], (1, 9)),
 ]
 
 EDGE = [

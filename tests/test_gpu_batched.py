@@ -63,7 +63,7 @@ def test_batched_symmetries(batch_fp32):
     for (a, b) in sectors:
         assert abs(e[(a, b)] - e[(b, a)]) <= 2e-6 * max(1.0, abs(e[(a, b)]))
         # SU(2): the (a+1, b-1) spectrum lies inside the (a, b) one when a >= b
-        if a >= b and b >= 1:
+        if a >= b and b >= 1 and a + 1 <= 12:
             assert e[(a + 1, b - 1)] >= e[(a, b)] - 2e-6 * max(1.0, abs(e[(a, b)]))
 
 
