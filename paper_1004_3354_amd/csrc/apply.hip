@@ -74,6 +74,15 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return s;
 }
 
+// value of m[q] for a runtime q < NMV (unrolled select; m stays in registers)
+template <int NMV>
+__device__ __forceinline__ int32_t pick(const int32_t (&m)[NMV > 0 ? NMV : 1], int q) {
+    int32_t v = -1;
+#pragma unroll
+    for (int k = 0; k < NMV; ++k) v = (k == q) ? m[k] : v;
+    return v;
+}
+
 // Row-window kernel.  A workgroup owns R consecutive rows and one window
 // [w0, w0 + wl) of down ranks (a run of states sharing their top bits, so most
 // down-spin hops stay inside it); the R x wl block of x is staged in LDS.  Each
@@ -83,11 +92,24 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // UPX = false: row-local part only (diagonal and 1 (x) H_dn), the first pass of
 // the two-pass schedule.  MODE 0 stores y; MODE 1 / 2 write per-workgroup
 // partials of <x,Hx>, <x,x> / ||Hx - theta x||^2 instead.
-template <typename TX, typename TA, int R, int BS, int MODE, bool UPX>
+template <typename TX, typename TA, int R, int BS, int MODE, bool UPX, bool PK = false>
 __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[2][BS / 64];
     TX *xs = reinterpret_cast<TX *>(smem_raw);
+    // packed hops: distinct amplitudes after the staged block
+    TA *amps = reinterpret_cast<TA *>(smem_raw + (((size_t)R * a.wmax * sizeof(TX) + 15) & ~(size_t)15));
+    // per-row partner lists (up hops, allowed four-fermion terms) staged once per
+    // workgroup, so the inner loops issue independent vector loads whose row
+    // addresses are LDS broadcasts
+    constexpr int UL = PK ? 32 : 1, XL = PK ? 16 : 1;
+    __shared__ int32_t u_src[R][UL];
+    __shared__ TA u_amp[R][UL];
+    __shared__ int32_t x_src[R][XL], x_tab[R][XL];
+    __shared__ TA x_amp[R][XL];
+    if constexpr (PK) {
+        for (int k = threadIdx.x; k < a.namp; k += BS) amps[k] = a.amp_tab[k];
+    }
 
     const int64_t ddn = a.ddn;
     const int nwin = a.nwin;
@@ -120,7 +142,24 @@ __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
         xb[r] = ok ? a.xl_off[u] : 0;
         xe[r] = ok ? a.xl_off[u + 1] : 0;
     }
-
+    if constexpr (PK && UPX) {
+        for (int k = threadIdx.x; k < R * UL; k += BS) {
+            const int r = k / UL, q = k - r * UL;
+            if (r < nr && hb[r] + q < he[r]) {
+                u_src[r][q] = a.up_tgt[hb[r] + q];
+                u_amp[r][q] = a.up_sa[hb[r] + q];
+            }
+        }
+        for (int k = threadIdx.x; k < R * XL; k += BS) {
+            const int r = k / XL, q = k - r * XL;
+            if (r < nr && xb[r] + q < xe[r]) {
+                x_src[r][q] = a.xl_src[xb[r] + q];
+                x_tab[r][q] = a.xl_tab[xb[r] + q];
+                x_amp[r][q] = a.xl_amp[xb[r] + q];
+            }
+        }
+        __syncthreads();
+    }
     double p0 = 0.0, p1 = 0.0;
     const int lane = threadIdx.x & 63;
     const int64_t dend = (int64_t)w0 + wl;
@@ -133,6 +172,11 @@ __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
         const TA edn = a.dn_e[d];
         const uint32_t sd = a.dn_st[d];
         const uint32_t cd = a.dn_c[d];
+        int32_t mvd[PK ? 8 : 1];
+        if constexpr (PK && UPX) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) mvd[q] = q < a.nmv_dn ? a.dn_mv[(int64_t)q * ddn + d] : -1;
+        }
         TA acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -142,11 +186,22 @@ __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
         for (int32_t e = eb + lane; e < ee; e += 256) {
             int32_t tt[4];
             TA ss[4];
+            if constexpr (PK) {
+                uint32_t pk[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const bool ok = e + 64 * k < ee;
-                tt[k] = ok ? a.dn_ell_tgt[e + 64 * k] : (int32_t)d;
-                ss[k] = ok ? a.dn_ell_sa[e + 64 * k] : (TA)0;
+                for (int k = 0; k < 4; ++k) pk[k] = e + 64 * k < ee ? a.dn_ell_pk[e + 64 * k] : (uint32_t)d;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    tt[k] = (int32_t)(pk[k] & 0xFFFFFu);
+                    ss[k] = amps[pk[k] >> 20];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const bool ok = e + 64 * k < ee;
+                    tt[k] = ok ? a.dn_ell_tgt[e + 64 * k] : (int32_t)d;
+                    ss[k] = ok ? a.dn_ell_sa[e + 64 * k] : (TA)0;
+                }
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -161,7 +216,29 @@ __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
                 }
             }
         }
-        if constexpr (UPX) {
+        if constexpr (UPX && PK) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int nu = he[r] - hb[r];
+#pragma unroll 4
+                for (int k = 0; k < nu; ++k) acc[r] += u_amp[r][k] * (TA)a.x[(int64_t)u_src[r][k] * ddn + d];
+                const int nxr = xe[r] - xb[r];
+#pragma unroll 2
+                for (int k = 0; k < nxr; ++k) {
+                    // the moves act on the lowest (impurity) bits, so the source row is
+                    // usually one of the staged rows and the column inside the window
+                    const int32_t m = pick<8>(mvd, x_tab[r][k]);
+                    const int64_t c = m >= 0 ? (int64_t)(m >> 1) : d;
+                    const int32_t rs = x_src[r][k] - (int32_t)u0;
+                    const int32_t lc = (int32_t)(c - w0);
+                    TA v;
+                    if ((uint32_t)rs < (uint32_t)nr && (uint32_t)lc < (uint32_t)wl) v = (TA)xs[rs * wl + lc];
+                    else v = (TA)a.x[(int64_t)x_src[r][k] * ddn + c];
+                    v = m >= 0 ? ((m & 1) ? -v : v) : (TA)0;
+                    acc[r] += x_amp[r][k] * v;
+                }
+            }
+        } else if constexpr (UPX) {
             // H_up (x) 1: partner rows, coalesced along d
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -265,6 +342,231 @@ __global__ __launch_bounds__(BS) void k_apply_band(ApplyArgs<TX, TA> a, int64_t 
     }
 }
 
+// Column-stationary kernel.  A workgroup owns one window of down ranks (at
+// most BS*CPT of them, a run of states sharing their top bits) and streams over
+// `rw` consecutive rows.  Each thread owns CPT columns and keeps everything
+// that depends only on the column in registers for the whole row stream: its
+// down-spin hop entries (target as a window-local LDS index, or the global
+// rank when the hop leaves the window, and signed amplitude), its one-spin
+// diagonal piece and bit string, and its entries of the down move tables of
+// the four-fermion terms.  Per row only independent gathers remain: the row
+// window (double-buffered in LDS), the up-spin partner rows and the
+// four-fermion partners, so many loads are in flight per wave.
+
+// Up-spin partners of row u at column d, unrolled to UMAX entries (padding
+// entries read the row itself with amplitude 0), so all loads are independent.
+template <typename TX, typename TA, int UMAX>
+__device__ __forceinline__ TA up_sum(const ApplyArgs<TX, TA> &a, int32_t hb, int32_t he, int64_t u, int64_t d) {
+    TA w[UMAX], v[UMAX];
+#pragma unroll
+    for (int k = 0; k < UMAX; ++k) {
+        const bool ok = hb + k < he;
+        const int64_t src = ok ? (int64_t)a.up_tgt[hb + k] : u;
+        w[k] = ok ? a.up_sa[hb + k] : (TA)0;
+        v[k] = (TA)a.x[src * a.ddn + d];
+    }
+    TA s = (TA)0;
+#pragma unroll
+    for (int k = 0; k < UMAX; ++k) s += w[k] * v[k];
+    return s;
+}
+
+// Four-fermion terms allowed on row u at column d, unrolled to XMAX entries.
+template <typename TX, typename TA, int NMV, int XMAX>
+__device__ __forceinline__ TA x_sum(const ApplyArgs<TX, TA> &a, const int32_t (&mvd)[NMV > 0 ? NMV : 1],
+                                    int32_t xb, int32_t xe, int64_t u, int64_t d) {
+    TA w[XMAX > 0 ? XMAX : 1], v[XMAX > 0 ? XMAX : 1];
+    int32_t mm[XMAX > 0 ? XMAX : 1];
+#pragma unroll
+    for (int k = 0; k < XMAX; ++k) {
+        const bool ok = xb + k < xe;
+        const int32_t m = ok ? pick<NMV>(mvd, a.xl_tab[xb + k]) : -1;
+        const int64_t src = ok ? (int64_t)a.xl_src[xb + k] : u;
+        w[k] = ok ? a.xl_amp[xb + k] : (TA)0;
+        mm[k] = m;
+        v[k] = (TA)a.x[src * a.ddn + (m >= 0 ? (int64_t)(m >> 1) : d)];
+    }
+    TA s = (TA)0;
+#pragma unroll
+    for (int k = 0; k < XMAX; ++k) {
+        const TA t = mm[k] >= 0 ? ((mm[k] & 1) ? -v[k] : v[k]) : (TA)0;
+        s += w[k] * t;
+    }
+    return s;
+}
+
+template <typename TX, typename TA, int BS, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX>
+__global__ __launch_bounds__(BS) void k_cs(ApplyArgs<TX, TA> a, int rw) {
+    // RR rows are processed per step (all their gathers in flight together);
+    // LDS holds two buffers of RR row windows.
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[2][BS / 64];
+    const int wm = a.wmax;
+    TX *bufs = reinterpret_cast<TX *>(smem_raw);
+    const int64_t ddn = a.ddn;
+    const int nwin = a.nwin;
+    const int64_t G = (a.dup + rw - 1) / rw;
+    const int64_t t = xcd_remap(blockIdx.x, G * nwin);
+    const int64_t g = t / nwin;
+    const int wi = (int)(t - g * nwin);
+    const int64_t u0 = g * rw;
+    const int nr = (int)((a.dup - u0) < rw ? (a.dup - u0) : rw);
+    const int32_t w0 = a.win[wi].x, wl = a.win[wi].y;
+
+    const int32_t li = (int32_t)threadIdx.x;
+    const bool act = li < wl;
+    const int64_t d = (int64_t)w0 + (act ? li : 0);
+    const int32_t ld = (int32_t)(d - w0);
+    int32_t lt[KMAX];
+    TA sa[KMAX];
+    {
+        const int32_t o = a.dn_off[d], n = a.dn_off[d + 1] - o;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const bool ok = k < n;
+            const int32_t tg = ok ? a.dn_tgt[o + k] : (int32_t)d;
+            const int32_t l = tg - w0;
+            lt[k] = ((uint32_t)l < (uint32_t)wl) ? l : (-1 - tg);
+            sa[k] = ok ? a.dn_sa[o + k] : (TA)0;
+        }
+    }
+    const TA edn = a.dn_e[d];
+    const uint32_t sdn = a.dn_st[d], cdn = a.dn_c[d];
+    int32_t mvd[NMV > 0 ? NMV : 1];
+#pragma unroll
+    for (int q = 0; q < NMV; ++q) mvd[q] = q < a.nmv_dn ? a.dn_mv[(int64_t)q * ddn + d] : -1;
+
+    // stage the first RR rows
+#pragma unroll
+    for (int rr = 0; rr < RR; ++rr)
+        if (rr < nr && act) bufs[rr * wm + li] = a.x[(u0 + rr) * ddn + w0 + li];
+    __syncthreads();
+
+    double p0 = 0.0, p1 = 0.0;
+    int step = 0;
+    for (int r0 = 0; r0 < nr; r0 += RR, ++step) {
+        TX *cur = bufs + ((step & 1) ? RR * wm : 0);
+        TX *nxt = bufs + ((step & 1) ? 0 : RR * wm);
+        TX pf[RR];
+#pragma unroll
+        for (int rr = 0; rr < RR; ++rr) {
+            const int rn = r0 + RR + rr;
+            pf[rr] = (rn < nr && act) ? a.x[(u0 + rn) * ddn + w0 + li] : (TX)0;
+        }
+        TA acc[RR], xv[RR];
+#pragma unroll
+        for (int rr = 0; rr < RR; ++rr) {
+            const int r = r0 + rr;
+            const int64_t u = u0 + (r < nr ? r : 0);
+            const TX *xrow = a.x + u * ddn;
+            xv[rr] = (TA)cur[rr * wm + ld];
+            acc[rr] = (a.up_e[u] + edn + cross_term(a, a.up_st[u], sdn, a.up_c[u], cdn)) * xv[rr];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const int32_t l = lt[k];
+                const TA v = l >= 0 ? (TA)cur[rr * wm + l] : (TA)xrow[-1 - l];
+                acc[rr] += sa[k] * v;
+            }
+        }
+        if constexpr (UPX) {
+#pragma unroll
+            for (int rr = 0; rr < RR; ++rr) {
+                const int r = r0 + rr;
+                const int64_t u = u0 + (r < nr ? r : 0);
+                const int32_t hb = r < nr ? a.up_off[u] : 0, he = r < nr ? a.up_off[u + 1] : 0;
+                acc[rr] += up_sum<TX, TA, KMAX>(a, hb, he, u, d);
+                if constexpr (NMV > 0) {
+                    const int32_t xb = r < nr ? a.xl_off[u] : 0, xe = r < nr ? a.xl_off[u + 1] : 0;
+                    acc[rr] += x_sum<TX, TA, NMV, XMAX>(a, mvd, xb, xe, u, d);
+                }
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int rr = 0; rr < RR; ++rr) {
+                const int r = r0 + rr;
+                if (r >= nr) break;
+                if constexpr (MODE == 0) {
+                    a.y[(u0 + r) * ddn + d] = (TX)acc[rr];
+                } else if constexpr (MODE == 1) {
+                    p0 += (double)xv[rr] * (double)acc[rr];
+                    p1 += (double)xv[rr] * (double)xv[rr];
+                } else {
+                    const double df = (double)acc[rr] - a.theta * (double)xv[rr];
+                    p0 += df * df;
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < RR; ++rr) nxt[rr * wm + li] = pf[rr];
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE != 0) {
+        const double s0 = block_sum<BS>(p0, red[0]);
+        const double s1 = block_sum<BS>(p1, red[1]);
+        if (threadIdx.x == 0) {
+            a.partials[2 * (int64_t)blockIdx.x] = s0;
+            a.partials[2 * (int64_t)blockIdx.x + 1] = s1;
+        }
+    }
+}
+
+// Column-stationary second pass over column bands (band-major): y += up-spin
+// term + four-fermion terms, each thread owning one column of the band and
+// streaming over `rw` rows.
+template <typename TX, typename TA, int BS, int RR, int UMAX, int NMV, int XMAX>
+__global__ __launch_bounds__(BS) void k_csb(ApplyArgs<TX, TA> a, int64_t band, int rw) {
+    const int64_t ddn = a.ddn;
+    const int64_t G = (a.dup + rw - 1) / rw;
+    const int64_t bi = blockIdx.x / G;
+    const int64_t g = blockIdx.x - bi * G;
+    const int64_t u0 = g * rw;
+    const int nr = (int)((a.dup - u0) < rw ? (a.dup - u0) : rw);
+    const int64_t d = bi * band + threadIdx.x;
+    if (threadIdx.x >= band || d >= ddn) return;
+    int32_t mvd[NMV > 0 ? NMV : 1];
+#pragma unroll
+    for (int q = 0; q < NMV; ++q) mvd[q] = q < a.nmv_dn ? a.dn_mv[(int64_t)q * ddn + d] : -1;
+    for (int r0 = 0; r0 < nr; r0 += RR) {
+        TA acc[RR];
+#pragma unroll
+        for (int rr = 0; rr < RR; ++rr) {
+            const int r = r0 + rr;
+            acc[rr] = r < nr ? (TA)a.y[(u0 + r) * ddn + d] : (TA)0;
+        }
+#pragma unroll
+        for (int rr = 0; rr < RR; ++rr) {
+            const int r = r0 + rr;
+            const int64_t u = u0 + (r < nr ? r : 0);
+            const int32_t hb = r < nr ? a.up_off[u] : 0, he = r < nr ? a.up_off[u + 1] : 0;
+            int32_t e = hb;
+            for (; e + 4 <= he; e += 4) {
+                const TA v0 = (TA)a.x[(int64_t)a.up_tgt[e] * ddn + d];
+                const TA v1 = (TA)a.x[(int64_t)a.up_tgt[e + 1] * ddn + d];
+                const TA v2 = (TA)a.x[(int64_t)a.up_tgt[e + 2] * ddn + d];
+                const TA v3 = (TA)a.x[(int64_t)a.up_tgt[e + 3] * ddn + d];
+                acc[rr] += a.up_sa[e] * v0 + a.up_sa[e + 1] * v1 + a.up_sa[e + 2] * v2 + a.up_sa[e + 3] * v3;
+            }
+            for (; e < he; ++e) acc[rr] += a.up_sa[e] * (TA)a.x[(int64_t)a.up_tgt[e] * ddn + d];
+            if constexpr (NMV > 0) {
+                const int32_t xb = r < nr ? a.xl_off[u] : 0, xe = r < nr ? a.xl_off[u + 1] : 0;
+                for (int32_t q = xb; q < xe; ++q) {
+                    const int32_t m = pick<NMV>(mvd, a.xl_tab[q]);
+                    const int64_t cc = m >= 0 ? (int64_t)(m >> 1) : d;
+                    TA v = (TA)a.x[(int64_t)a.xl_src[q] * ddn + cc];
+                    v = m >= 0 ? ((m & 1) ? -v : v) : (TA)0;
+                    acc[rr] += a.xl_amp[q] * v;
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RR; ++rr) {
+            const int r = r0 + rr;
+            if (r < nr) a.y[(u0 + r) * ddn + d] = (TX)acc[rr];
+        }
+    }
+}
+
 // ---------------------------------------------------------- variant table --
 // kind 0: single pass.  kind 1: two passes (row-local, then banded up spin).
 struct Variant {
@@ -278,6 +580,14 @@ static const Variant kVariants[] = {
     {0, 16, 256, 0, "rw_r16_b256"},        {0, 8, 512, 0, "rw_r8_b512"},
     {1, 8, 256, 512, "tp_r8_band512"},     {1, 8, 256, 2048, "tp_r8_band2048"},
     {1, 16, 256, 512, "tp_r16_band512"},   {1, 16, 256, 2048, "tp_r16_band2048"},
+    {2, 2, 512, 32, "cs_rr2_rw32"},        {2, 4, 512, 32, "cs_rr4_rw32"},
+    {2, 4, 512, 8, "cs_rr4_rw8"},          {2, 4, 512, 128, "cs_rr4_rw128"},
+    {3, 4, 512, 32, "cstp_rr4_rw32"},      {3, 2, 512, 32, "cstp_rr2_rw32"},
+    {4, 1, 256, 0, "rwpk_r1_b256"},        {4, 2, 512, 0, "rwpk_r2_b512"},
+    {4, 4, 512, 0, "rwpk_r4_b512"},        {4, 2, 256, 0, "rwpk_r2_b256"},
+    {5, 8, 256, 512, "tppk_r8_band512"},   {5, 16, 256, 512, "tppk_r16_band512"},
+    {4, 4, 512, 4096, "rwpk_r4_b512_w4k"},  {4, 8, 512, 2048, "rwpk_r8_b512_w2k"},
+    {4, 4, 1024, 0, "rwpk_r4_b1024"},       {4, 2, 512, 4096, "rwpk_r2_b512_w4k"},
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static constexpr int64_t kDynBudget = 163840 - 8192;  // LDS left for the staged x block
@@ -364,6 +674,13 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.dn_ell_off = Dn.ell_off.as<int32_t>();
     a.dn_ell_tgt = Dn.ell_tgt.as<int32_t>();
     a.dn_ell_sa = Dn.ell_sa64.as<double>();
+    a.dn_off = Dn.off.as<int32_t>();
+    a.dn_tgt = Dn.tgt.as<int32_t>();
+    a.dn_sa = Dn.sa64.as<double>();
+    a.nmv_dn = Dn.nmv;
+    a.dn_ell_pk = Dn.ell_pk.as<uint32_t>();
+    a.amp_tab = Dn.amp64.as<double>();
+    a.namp = Dn.namp;
     a.dn_e = Dn.ediag64.as<double>();
     a.dn_st = Dn.states.as<uint32_t>();
     a.dn_c = Dn.cidx.as<uint8_t>();
@@ -404,6 +721,13 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.dn_ell_off = Dn.ell_off.as<int32_t>();
     a.dn_ell_tgt = Dn.ell_tgt.as<int32_t>();
     a.dn_ell_sa = Dn.ell_sa32.as<float>();
+    a.dn_off = Dn.off.as<int32_t>();
+    a.dn_tgt = Dn.tgt.as<int32_t>();
+    a.dn_sa = Dn.sa32.as<float>();
+    a.nmv_dn = Dn.nmv;
+    a.dn_ell_pk = Dn.ell_pk.as<uint32_t>();
+    a.amp_tab = Dn.amp32.as<float>();
+    a.namp = Dn.namp;
     a.dn_e = Dn.ediag32.as<float>();
     a.dn_st = Dn.states.as<uint32_t>();
     a.dn_c = Dn.cidx.as<uint8_t>();
@@ -447,14 +771,18 @@ static void allow_lds(K kern) {
     }
 }
 
-template <typename TX, typename TA, int R, int BS, int MODE, bool UPX>
-static int64_t launch_rw(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s) {
+template <typename TX, typename TA, int R, int BS, int MODE, bool UPX, bool PK = false>
+static int64_t launch_rw(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t wcap = 0) {
     int nwin = 0, wmax = 0;
-    a.win = windows_for(h, kDynBudget / (int64_t)(R * sizeof(TX)), &nwin, &wmax);
+    const int64_t amp_bytes = PK ? (int64_t)h->sp[1].namp * (int64_t)sizeof(TA) + 16 : 0;
+    int64_t cap = (kDynBudget - amp_bytes) / (int64_t)(R * sizeof(TX));
+    if (wcap > 0 && wcap < cap) cap = wcap;
+    a.win = windows_for(h, cap, &nwin, &wmax);
     a.nwin = nwin;
+    a.wmax = wmax;
     const int64_t G = (a.dup + R - 1) / R;
-    const size_t shm = (size_t)R * (size_t)wmax * sizeof(TX);
-    auto kern = k_apply<TX, TA, R, BS, MODE, UPX>;
+    const size_t shm = (((size_t)R * (size_t)wmax * sizeof(TX) + 15) & ~(size_t)15) + (size_t)amp_bytes;
+    auto kern = k_apply<TX, TA, R, BS, MODE, UPX, PK>;
     allow_lds(kern);
     kern<<<(unsigned)(G * nwin), BS, shm, s>>>(a);
     ED_LAUNCH_CHECK();
@@ -468,6 +796,75 @@ static void launch_band(const ApplyArgs<TX, TA> &a, int64_t band, hipStream_t s)
     const int64_t nb = (a.ddn + band - 1) / band;
     k_apply_band<TX, TA, RB, 256><<<(unsigned)(G * nb), 256, 0, s>>>(a, band);
     ED_LAUNCH_CHECK();
+}
+
+// register-tile sizes of the column-stationary kernels
+static int cs_kmax(const ed_ham_s *h) {
+    const int m = std::max(h->sp[0].max_hops, h->sp[1].max_hops);
+    return m <= 8 ? 8 : (m <= 16 ? 16 : (m <= 32 ? 32 : 0));
+}
+static int cs_nmv(const ed_ham_s *h) {
+    const int n = h->sp[1].nmv;
+    return (h->nx == 0) ? 0 : (n <= 8 ? 8 : -1);
+}
+static int cs_xmax(const ed_ham_s *h) {
+    return h->xl_max <= 4 ? 4 : (h->xl_max <= 8 ? 8 : 0);
+}
+
+template <typename TX, typename TA, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX>
+static int64_t launch_cs_k(ed_ham_s *h, ApplyArgs<TX, TA> a, int rw, hipStream_t s) {
+    constexpr int BS = 512;
+    int nwin = 0, wmax = 0;
+    a.win = windows_for(h, (int64_t)BS, &nwin, &wmax);
+    a.nwin = nwin;
+    a.wmax = wmax;
+    const int64_t G = (a.dup + rw - 1) / rw;
+    const size_t shm = 2 * (size_t)RR * (size_t)wmax * sizeof(TX);
+    k_cs<TX, TA, BS, RR, KMAX, NMV, XMAX, MODE, UPX><<<(unsigned)(G * nwin), BS, shm, s>>>(a, rw);
+    ED_LAUNCH_CHECK();
+    return G * nwin;
+}
+
+template <typename TX, typename TA, int RR, int MODE, bool UPX, int KMAX>
+static int64_t launch_cs_km(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
+    const int nm = cs_nmv(h), xm = cs_xmax(h);
+    if (nm == 0) return launch_cs_k<TX, TA, RR, KMAX, 0, 0, MODE, UPX>(h, a, rw, s);
+    if (nm == 8 && xm == 4) return launch_cs_k<TX, TA, RR, KMAX, 8, 4, MODE, UPX>(h, a, rw, s);
+    if (nm == 8 && xm == 8) return launch_cs_k<TX, TA, RR, KMAX, 8, 8, MODE, UPX>(h, a, rw, s);
+    fail(ED_EINVAL, "column-stationary schedule does not fit this Hamiltonian");
+}
+
+template <typename TX, typename TA, int RR, int MODE, bool UPX>
+static int64_t launch_cs(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
+    const int km = cs_kmax(h);
+    if (km == 8) return launch_cs_km<TX, TA, RR, MODE, UPX, 8>(h, a, rw, s);
+    if (km == 16) return launch_cs_km<TX, TA, RR, MODE, UPX, 16>(h, a, rw, s);
+    if (km == 32) return launch_cs_km<TX, TA, RR, MODE, UPX, 32>(h, a, rw, s);
+    fail(ED_EINVAL, "column-stationary schedule does not fit this Hamiltonian");
+}
+
+template <typename TX, typename TA, int RR, int UMAX>
+static void launch_csb_u(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
+    constexpr int BS = 512;
+    const int64_t band = BS;
+    const int64_t G = (a.dup + rw - 1) / rw;
+    const int64_t nb = (a.ddn + band - 1) / band;
+    const int nm = cs_nmv(h), xm = cs_xmax(h);
+    if (nm == 0)
+        k_csb<TX, TA, BS, RR, UMAX, 0, 0><<<(unsigned)(G * nb), BS, 0, s>>>(a, band, rw);
+    else if (xm == 4)
+        k_csb<TX, TA, BS, RR, UMAX, 8, 4><<<(unsigned)(G * nb), BS, 0, s>>>(a, band, rw);
+    else
+        k_csb<TX, TA, BS, RR, UMAX, 8, 8><<<(unsigned)(G * nb), BS, 0, s>>>(a, band, rw);
+    ED_LAUNCH_CHECK();
+}
+
+template <typename TX, typename TA, int RR>
+static void launch_csb(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
+    const int km = cs_kmax(h);
+    if (km == 8) launch_csb_u<TX, TA, RR, 8>(h, a, rw, s);
+    else if (km == 16) launch_csb_u<TX, TA, RR, 16>(h, a, rw, s);
+    else launch_csb_u<TX, TA, RR, 32>(h, a, rw, s);
 }
 
 template <typename TX, typename TA>
@@ -484,6 +881,22 @@ static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipSt
         case 7: launch_rw<TX, TA, 8, 256, 0, false>(h, a, s); launch_band(a, V.band, s); break;
         case 8:
         case 9: launch_rw<TX, TA, 16, 256, 0, false>(h, a, s); launch_band(a, V.band, s); break;
+        case 10: launch_cs<TX, TA, 2, 0, true>(h, a, (int)V.band, s); break;
+        case 11:
+        case 12:
+        case 13: launch_cs<TX, TA, 4, 0, true>(h, a, (int)V.band, s); break;
+        case 14: launch_cs<TX, TA, 4, 0, false>(h, a, (int)V.band, s); launch_csb<TX, TA, 4>(h, a, 32, s); break;
+        case 15: launch_cs<TX, TA, 2, 0, false>(h, a, (int)V.band, s); launch_csb<TX, TA, 2>(h, a, 32, s); break;
+        case 16: launch_rw<TX, TA, 1, 256, 0, true, true>(h, a, s); break;
+        case 17: launch_rw<TX, TA, 2, 512, 0, true, true>(h, a, s); break;
+        case 18: launch_rw<TX, TA, 4, 512, 0, true, true>(h, a, s); break;
+        case 19: launch_rw<TX, TA, 2, 256, 0, true, true>(h, a, s); break;
+        case 20: launch_rw<TX, TA, 8, 256, 0, false, true>(h, a, s); launch_band(a, V.band, s); break;
+        case 21: launch_rw<TX, TA, 16, 256, 0, false, true>(h, a, s); launch_band(a, V.band, s); break;
+        case 22: launch_rw<TX, TA, 4, 512, 0, true, true>(h, a, s, V.band); break;
+        case 23: launch_rw<TX, TA, 8, 512, 0, true, true>(h, a, s, V.band); break;
+        case 24: launch_rw<TX, TA, 4, 1024, 0, true, true>(h, a, s); break;
+        case 25: launch_rw<TX, TA, 2, 512, 0, true, true>(h, a, s, V.band); break;
         default: fail(ED_EINVAL, "bad apply variant %d", v);
     }
 }
@@ -491,7 +904,12 @@ static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipSt
 static bool variant_fits(const ed_ham_s *h, int v, size_t elem) {
     if (v < 0 || v >= kNumVariants) return false;
     const Variant &V = kVariants[v];
-    if (V.kind == 1 && h->nx == 0 && h->sp[0].nnz == 0) return false;  // nothing for the second pass
+    if ((V.kind == 1 || V.kind == 3) && h->nx == 0 && h->sp[0].nnz == 0) return false;  // no second pass
+    if ((V.kind == 2 || V.kind == 3) && (cs_kmax(h) == 0 || cs_nmv(h) < 0 || (h->nx > 0 && cs_xmax(h) == 0)))
+        return false;
+    if (V.kind >= 4 && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->sp[1].nmv > 8))
+        return false;
+    if (V.kind == 5 && h->nx == 0 && h->sp[0].nnz == 0) return false;
     return true;
 }
 

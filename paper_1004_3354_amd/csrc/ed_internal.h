@@ -129,6 +129,12 @@ struct SpinTab {
     DevMem ell_off;           // int32 [nslices+1] start (in entries) of each 64-state slice
     DevMem ell_tgt;           // int32 [ell_off[nslices]]  (slice, hop k, lane) -> target
     DevMem ell_sa64, ell_sa32;
+    // packed sliced ELL: target rank (bits 0..19) | index into amp table (bits 20..31);
+    // amp[0] = 0 for padding.  Built when dim <= 2^20 and <= 4095 distinct amplitudes.
+    bool pk_ok = false;
+    int namp = 0;
+    DevMem ell_pk;            // uint32 [ell_off[nslices]]
+    DevMem amp64, amp32;      // distinct signed amplitudes
     DevMem ediag64, ediag32;  // one-spin diagonal piece: eps n + same-spin density terms
     DevMem cidx;              // uint8 [dim] bits of the state on the cross-term support
     int nmv = 0;              // number of move tables
@@ -176,6 +182,7 @@ struct ed_ham_s {
     // per up state: the four-fermion terms whose up move is allowed, as CSR
     // (source up rank, down move table, signed amplitude)
     ed::DevMem xl_off, xl_src, xl_tab, xl_amp64, xl_amp32;
+    int xl_max = 0;             // largest list length
     ed::ApplyPlan plan;
     ed::DevMem redbuf;          // small FP64 reduction scratch owned by the handle
     size_t redbuf_doubles = 0;
@@ -201,9 +208,15 @@ struct ApplyArgs {
     const uint32_t *up_st;
     const uint8_t *up_c;
     const int32_t *up_mv;
-    // columns (spin down): sliced ELL
+    // columns (spin down): sliced ELL and CSR
     const int32_t *dn_ell_off, *dn_ell_tgt;
     const TA *dn_ell_sa, *dn_e;
+    const int32_t *dn_off, *dn_tgt;
+    const TA *dn_sa;
+    int nmv_dn;
+    const uint32_t *dn_ell_pk;
+    const TA *amp_tab;
+    int namp;
     const uint32_t *dn_st;
     const uint8_t *dn_c;
     const int32_t *dn_mv;
@@ -225,6 +238,7 @@ struct ApplyArgs {
     // down-spin windows staged in LDS: (first rank, length) per window
     const int2 *win;
     int nwin;
+    int wmax;
 };
 
 // Build all tables of a Hamiltonian handle (tables.hip).

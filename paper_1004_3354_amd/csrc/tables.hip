@@ -148,6 +148,12 @@ __global__ void k_ell_fill(const int64_t *off64, int64_t dim, int64_t nslices, c
     }
 }
 
+// packed ELL entries from the unpacked ones and the amplitude index map
+__global__ void k_ell_pack(const int32_t *etgt, const int32_t *eamp_idx, int64_t n, uint32_t *out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = (uint32_t)etgt[e] | ((uint32_t)eamp_idx[e] << 20);
+}
+
 // ------------------------------------------------------- diagonal pieces ----
 // e_s(state) = sum_i eps_i n_i + sum_{i<j} w_ij n_i n_j  (FP64, cast for FP32)
 __global__ void k_ediag(const uint32_t *st, int64_t dim, int ns, const double *eps, const double *wss,
@@ -318,6 +324,40 @@ static void build_spin(ed_ham_s *h, int s, const BasisData &b, const ed_params *
         for (int64_t v : hc) m = std::max(m, v);
         t.max_hops = (int)m;
     }
+    // packed form: distinct signed amplitudes (index 0 is the zero of the padding)
+    t.pk_ok = false;
+    if (dim <= (1 << 20) && nell > 0) {
+        std::vector<double> esa((size_t)nell);
+        ED_HIP(hipMemcpy(esa.data(), t.ell_sa64.p, (size_t)nell * sizeof(double), hipMemcpyDeviceToHost));
+        std::vector<double> vals{0.0};
+        std::map<double, int> idx;
+        idx[0.0] = 0;
+        std::vector<int32_t> ai((size_t)nell);
+        bool ok = true;
+        for (int64_t e = 0; e < nell && ok; ++e) {
+            auto it = idx.find(esa[e]);
+            if (it == idx.end()) {
+                if (vals.size() >= 4095) { ok = false; break; }
+                it = idx.emplace(esa[e], (int)vals.size()).first;
+                vals.push_back(esa[e]);
+            }
+            ai[e] = it->second;
+        }
+        if (ok) {
+            DevMem dai;
+            upload(dai, ai);
+            t.ell_pk.alloc((size_t)nell * sizeof(uint32_t));
+            k_ell_pack<<<grid_for(nell, 256, 1 << 16), 256>>>(t.ell_tgt.as<int32_t>(), dai.as<int32_t>(), nell,
+                                                            t.ell_pk.as<uint32_t>());
+            ED_LAUNCH_CHECK();
+            upload(t.amp64, vals);
+            std::vector<float> v32(vals.begin(), vals.end());
+            upload(t.amp32, v32);
+            t.namp = (int)vals.size();
+            t.pk_ok = true;
+            ED_HIP(hipDeviceSynchronize());
+        }
+    }
 
     // one-spin diagonal piece
     std::vector<double> eps(p->eps + (size_t)s * ns, p->eps + (size_t)(s + 1) * ns);
@@ -452,6 +492,13 @@ static void build_xterms(ed_ham_s *h, const ed_params *p) {
     ED_LAUNCH_CHECK();
     int64_t nl = 0;
     ED_HIP(hipMemcpy(&nl, off64.as<int64_t>() + dup, sizeof(int64_t), hipMemcpyDeviceToHost));
+    {
+        std::vector<int64_t> hc((size_t)dup);
+        ED_HIP(hipMemcpy(hc.data(), cnt.p, (size_t)dup * sizeof(int64_t), hipMemcpyDeviceToHost));
+        int64_t mx = 0;
+        for (int64_t v : hc) mx = std::max(mx, v);
+        h->xl_max = (int)mx;
+    }
     h->xl_off.alloc((size_t)(dup + 1) * sizeof(int32_t));
     h->xl_src.alloc((size_t)std::max<int64_t>(nl, 1) * sizeof(int32_t));
     h->xl_tab.alloc((size_t)std::max<int64_t>(nl, 1) * sizeof(int32_t));
