@@ -324,7 +324,7 @@ def main():
     # ---- time to E0, FP32-mixed vs FP64, same start vector and target
     e0 = None
     if not args.no_e0:
-        e0 = time_to_e0(2, [ed.ED_FP32, ed.ED_FP64], max_basis=150, tol=1e-7, seed_idx=2)
+        e0 = time_to_e0(2, [ed.ED_FP32, ed.ED_FP64], max_basis=100, tol=1e-7, seed_idx=2)
     e0_18 = None
     if args.e0_ns18:
         e0_18 = time_to_e0(4, [ed.ED_FP32, ed.ED_FP64], max_basis={ed.ED_FP32: 24, ed.ED_FP64: 11},

@@ -19,8 +19,11 @@
 // entries are in a 64-state sliced ELL layout, one coalesced load per hop per
 // wave, reused across the R rows.  Workgroup -> row-group mapping is XCD-aware
 // (consecutive row groups stay on one XCD so shared partner rows hit its L2).
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include "ed_internal.h"
 
@@ -395,7 +398,8 @@ __device__ __forceinline__ TA x_sum(const ApplyArgs<TX, TA> &a, const int32_t (&
     return s;
 }
 
-template <typename TX, typename TA, int BS, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX>
+template <typename TX, typename TA, int BS, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX,
+          bool XROW = false>
 __global__ __launch_bounds__(BS) void k_cs(ApplyArgs<TX, TA> a, int rw) {
     // RR rows are processed per step (all their gathers in flight together);
     // LDS holds two buffers of RR row windows.
@@ -479,6 +483,15 @@ __global__ __launch_bounds__(BS) void k_cs(ApplyArgs<TX, TA> a, int rw) {
                     const int32_t xb = r < nr ? a.xl_off[u] : 0, xe = r < nr ? a.xl_off[u + 1] : 0;
                     acc[rr] += x_sum<TX, TA, NMV, XMAX>(a, mvd, xb, xe, u, d);
                 }
+            }
+        } else if constexpr (XROW && NMV > 0) {
+            // four-fermion terms in the row pass (their partners are nearby rows)
+#pragma unroll
+            for (int rr = 0; rr < RR; ++rr) {
+                const int r = r0 + rr;
+                const int64_t u = u0 + (r < nr ? r : 0);
+                const int32_t xb = r < nr ? a.xl_off[u] : 0, xe = r < nr ? a.xl_off[u + 1] : 0;
+                acc[rr] += x_sum<TX, TA, NMV, XMAX>(a, mvd, xb, xe, u, d);
             }
         }
         if (act) {
@@ -567,12 +580,442 @@ __global__ __launch_bounds__(BS) void k_csb(ApplyArgs<TX, TA> a, int64_t band, i
     }
 }
 
+// ------------------------------------------------------ transposed tiles --
+// Row-tile kernel with the tile transposed in LDS.  A workgroup owns R rows and
+// one window of down ranks; LDS holds the tile column-major (xs[l*R + r]), so
+// one LDS read returns a column's values for all R rows and every down-spin
+// hop entry serves R output elements.  Each thread owns four consecutive
+// columns: x rows, partner rows and y move as 16-byte accesses (rows need only
+// element alignment), and the down-spin entries of its four states come from
+// the four-state packed ELL in one 16-byte load.  Thread chunks start at a
+// multiple of 256 columns so that a wave covers exactly one ELL slice.
+// UPX = true: full product.  UPX = false: everything but H_up (x) 1 (the row
+// pass of the two-pass schedule).  NTY: y is stored non-temporally (kept out of
+// the caches so that x stays resident).
+template <typename TX>
+struct V4 {
+    typedef TX t __attribute__((ext_vector_type(4), aligned(sizeof(TX))));
+};
+template <typename TX, int R>
+struct RV {
+    typedef TX t __attribute__((ext_vector_type(R)));
+};
+template <typename TX>
+struct RV<TX, 1> {
+    typedef TX t;
+};
+template <typename TX, int R>
+__device__ __forceinline__ TX rv_get(const typename RV<TX, R>::t &v, int r) {
+    if constexpr (R == 1) return v;
+    else return v[r];
+}
+template <typename TX, bool NT>
+__device__ __forceinline__ void st4(TX *p, typename V4<TX>::t v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<typename V4<TX>::t *>(p));
+    else *reinterpret_cast<typename V4<TX>::t *>(p) = v;
+}
+template <typename TX>
+__device__ __forceinline__ typename V4<TX>::t ld4(const TX *p) {
+    return *reinterpret_cast<const typename V4<TX>::t *>(p);
+}
+
+// cross term with the per-site U values and the 4^koff table taken from LDS
+// copies (xtl is used when koff <= 4)
+template <typename TX, typename TA>
+__device__ __forceinline__ TA cross_term_l(const ApplyArgs<TX, TA> &a, const TA *usl, const TA *xtl, uint32_t su,
+                                           uint32_t sd, uint32_t cu, uint32_t cd) {
+    TA c = (TA)0;
+    if (a.umode == 1) {
+        c = a.U0 * (TA)__popc(su & sd & a.umask);
+    } else if (a.umode == 2) {
+        uint32_t m = su & sd & a.umask;
+        while (m) {
+            c += usl[__ffs(m) - 1];
+            m &= m - 1u;
+        }
+    }
+    if (a.koff) c += a.koff <= 4 ? xtl[(cu << a.koff) | cd] : a.xtab[(cu << a.koff) | cd];
+    return c;
+}
+
+template <typename TX, typename TA, int R, int BS, bool UPX, bool NTY, bool BOND = false>
+__global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
+    using RVt = typename RV<TX, R>::t;
+    using V = typename V4<TX>::t;
+    constexpr int UL = 32, XL = 16;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    TX *xs = reinterpret_cast<TX *>(smem_raw);
+    TA *amps = reinterpret_cast<TA *>(smem_raw + (((size_t)R * a.wmax * sizeof(TX) + 15) & ~(size_t)15));
+    __shared__ int32_t u_src[R][UL];
+    __shared__ TA u_amp[R][UL];
+    __shared__ int32_t x_src[R][XL], x_tab[R][XL];
+    __shared__ TA x_amp[R][XL];
+    __shared__ TA usl[32], xtl[256];
+    if constexpr (!BOND) {
+        for (int k = threadIdx.x; k < a.namp; k += BS) amps[k] = a.amp_tab[k];
+    }
+    if (a.umode == 2)
+        for (int k = threadIdx.x; k < 32; k += BS) usl[k] = a.usite[k];
+    if (a.koff && a.koff <= 4)
+        for (int k = threadIdx.x; k < (1 << (2 * a.koff)); k += BS) xtl[k] = a.xtab[k];
+
+    const int64_t ddn = a.ddn;
+    const int nwin = a.nwin;
+    const int64_t G = a.tiles ? (int64_t)a.ntiles : (a.dup + R - 1) / R;
+    const int64_t t = xcd_remap(blockIdx.x, G * nwin);
+    const int64_t g = t / nwin;
+    const int wi = (int)(t - g * nwin);
+    int64_t u0 = g * R;
+    int nr = (int)((a.dup - u0) < R ? (a.dup - u0) : R);
+    if (a.tiles) {
+        u0 = a.tiles[g].x;
+        nr = a.tiles[g].y;
+    }
+    const int32_t w0 = a.win[wi].x, wl = a.win[wi].y;
+    const int64_t cb = (int64_t)(w0 & ~255), cend = (int64_t)w0 + wl;
+
+    TA eu[R];
+    uint32_t su[R], cu[R];
+    int nu[R], nxl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool ok = r < nr;
+        const int64_t u = u0 + (ok ? r : 0);
+        eu[r] = ok ? a.up_e[u] : (TA)0;
+        su[r] = ok ? a.up_st[u] : 0u;
+        cu[r] = ok ? a.up_c[u] : 0u;
+        const int32_t hb = a.up_off[u], he = a.up_off[u + 1];
+        const int n = ok && UPX ? he - hb : 0;
+        nu[r] = (n + 3) & ~3;
+        nxl[r] = ok ? a.xl_off[u + 1] - a.xl_off[u] : 0;
+        for (int k = threadIdx.x; k < nu[r]; k += BS) {
+            u_src[r][k] = k < n ? a.up_tgt[hb + k] : (int32_t)u;
+            u_amp[r][k] = k < n ? a.up_sa[hb + k] : (TA)0;
+        }
+        const int32_t xb = a.xl_off[u];
+        for (int k = threadIdx.x; k < nxl[r]; k += BS) {
+            x_src[r][k] = a.xl_src[xb + k];
+            x_tab[r][k] = a.xl_tab[xb + k];
+            x_amp[r][k] = a.xl_amp[xb + k];
+        }
+    }
+    // stage the tile, transposed
+    for (int64_t c = cb + 4 * (int64_t)threadIdx.x; c < cend; c += 4 * BS) {
+        if (c + 4 <= w0) continue;
+        TX v[R][4];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[r][j] = (TX)0;
+        if (c >= w0 && c + 4 <= cend) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r < nr) {
+                    const typename V4<TX>::t q = ld4(a.x + (u0 + r) * ddn + c);
+                    v[r][0] = q.x; v[r][1] = q.y; v[r][2] = q.z; v[r][3] = q.w;
+                }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (r < nr && c + j >= w0 && c + j < cend) v[r][j] = a.x[(u0 + r) * ddn + c + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t l = c + j - w0;
+            if (l >= 0 && l < wl) {
+                RVt o;
+                if constexpr (R == 1) o = v[0][j];
+                else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) o[r] = v[r][j];
+                }
+                *reinterpret_cast<RVt *>(xs + l * R) = o;
+            }
+        }
+    }
+    __syncthreads();
+    auto chunk = [&](auto full_tag, int64_t c) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        TA edn[4];
+        uint32_t sd[4], cd[4];
+        if constexpr (FULL) {
+            const V e = *reinterpret_cast<const V *>(a.dn_e + c);  // c is a multiple of 4
+            const uint4 st = *reinterpret_cast<const uint4 *>(a.dn_st + c);
+            const uint32_t cc = *reinterpret_cast<const uint32_t *>(a.dn_c + c);
+            edn[0] = (TA)e.x; edn[1] = (TA)e.y; edn[2] = (TA)e.z; edn[3] = (TA)e.w;
+            sd[0] = st.x; sd[1] = st.y; sd[2] = st.z; sd[3] = st.w;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cd[j] = (cc >> (8 * j)) & 0xFFu;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool ok = c + j < ddn;
+                edn[j] = ok ? (TA)a.dn_e[c + j] : (TA)0;
+                sd[j] = ok ? a.dn_st[c + j] : 0u;
+                cd[j] = ok ? (uint32_t)a.dn_c[c + j] : 0u;
+            }
+        }
+        TA acc[R][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t l = c + j - w0;
+            RVt v = (RVt)0;
+            if (FULL || (l >= 0 && l < wl)) v = *reinterpret_cast<const RVt *>(xs + l * R);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                acc[r][j] = (eu[r] + edn[j] + cross_term_l(a, usl, xtl, su[r], sd[j], cu[r], cd[j])) *
+                            (TA)rv_get<TX, R>(v, r);
+        }
+        // 1 (x) H_dn
+        if constexpr (BOND) {
+            // slot k is bond k for every state: uniform amplitude, sign and
+            // activity from the entry
+            const int lane = threadIdx.x & 63;
+            const int nb = a.nbond;
+            const uint4 *ep = a.dn_ell4b + ((c >> 8) * nb) * 64 + lane;
+#pragma unroll 2
+            for (int k = 0; k < nb; ++k) {
+                const uint4 e = ep[(int64_t)k * 64];
+                const TA hk = a.dn_bamp[k];
+                const uint32_t ev[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int32_t t = (int32_t)(ev[j] & 0xFFFFFu);
+                    const TA am = (ev[j] & (1u << 21)) ? ((ev[j] & (1u << 20)) ? -hk : hk) : (TA)0;
+                    const int32_t l = t - w0;
+                    if ((uint32_t)l < (uint32_t)wl) {
+                        const RVt v = *reinterpret_cast<const RVt *>(xs + (int64_t)l * R);
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[r][j] += am * (TA)rv_get<TX, R>(v, r);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            acc[r][j] += am * (TA)a.x[(u0 + (r < nr ? r : 0)) * ddn + t];
+                    }
+                }
+            }
+        } else {
+            const int lane = threadIdx.x & 63;
+            const int64_t sl = c >> 8;
+            const int32_t eb = a.dn_ell4_off[sl];
+            const int32_t kk = (a.dn_ell4_off[sl + 1] - eb) >> 6;
+            const uint4 *ep = a.dn_ell4 + eb + lane;
+#pragma unroll 2
+            for (int32_t k = 0; k < kk; ++k) {
+                const uint4 e = ep[(int64_t)k * 64];
+                const uint32_t ev[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int32_t t = (int32_t)(ev[j] & 0xFFFFFu);
+                    const TA am = amps[ev[j] >> 20];
+                    const int32_t l = t - w0;
+                    if ((uint32_t)l < (uint32_t)wl) {
+                        const RVt v = *reinterpret_cast<const RVt *>(xs + (int64_t)l * R);
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[r][j] += am * (TA)rv_get<TX, R>(v, r);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            acc[r][j] += am * (TA)a.x[(u0 + (r < nr ? r : 0)) * ddn + t];
+                    }
+                }
+            }
+        }
+        // four-fermion terms: the rows' lists are ordered by down move, so each
+        // move table entry is loaded once for all rows of the tile
+        if (a.nx) {
+            int p[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[r] = 0;
+            for (int q = 0; q < a.nmv_dn; ++q) {
+                bool any = false;
+#pragma unroll
+                for (int r = 0; r < R; ++r) any |= (p[r] < nxl[r] && x_tab[r][p[r]] == q);
+                if (!any) continue;
+                int32_t m[4];
+                const int32_t *mp = a.dn_mv + (int64_t)q * ddn + c;
+                if constexpr (FULL) {
+                    int32_t tmp[4];
+                    __builtin_memcpy(tmp, mp, 16);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) m[j] = tmp[j];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) m[j] = c + j < ddn ? mp[j] : -1;
+                }
+                int32_t col[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) col[j] = m[j] >= 0 ? (m[j] >> 1) : (int32_t)(c + j < ddn ? c + j : ddn - 1);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    while (p[r] < nxl[r] && x_tab[r][p[r]] == q) {
+                        const int k = p[r]++;
+                        const int32_t srow = x_src[r][k];
+                        const TA am = x_amp[r][k];
+                        const int32_t rs = srow - (int32_t)u0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int32_t lc = col[j] - w0;
+                            TA v;
+                            if ((uint32_t)rs < (uint32_t)nr && (uint32_t)lc < (uint32_t)wl)
+                                v = (TA)xs[(int64_t)lc * R + rs];
+                            else
+                                v = (TA)a.x[(int64_t)srow * ddn + col[j]];
+                            v = m[j] >= 0 ? ((m[j] & 1) ? -v : v) : (TA)0;
+                            acc[r][j] += am * v;
+                        }
+                    }
+                }
+            }
+        }
+        // H_up (x) 1: partner rows, four independent 16-byte loads at a time
+        if constexpr (UPX) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (r >= nr) break;
+                for (int k = 0; k < nu[r]; k += 4) {
+                    if constexpr (FULL) {
+                        V v[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) v[i] = ld4(a.x + (int64_t)u_src[r][k + i] * ddn + c);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const TA am = u_amp[r][k + i];
+                            acc[r][0] += am * (TA)v[i].x;
+                            acc[r][1] += am * (TA)v[i].y;
+                            acc[r][2] += am * (TA)v[i].z;
+                            acc[r][3] += am * (TA)v[i].w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const TA am = u_amp[r][k + i];
+                            const TX *row = a.x + (int64_t)u_src[r][k + i] * ddn;
+#pragma unroll
+                            for (int j = 0; j < 4; ++j)
+                                if (c + j < ddn) acc[r][j] += am * (TA)row[c + j];
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r >= nr) break;
+            TX *yr = a.y + (u0 + r) * ddn;
+            if constexpr (FULL) {
+                V o;
+                o.x = (TX)acc[r][0]; o.y = (TX)acc[r][1]; o.z = (TX)acc[r][2]; o.w = (TX)acc[r][3];
+                st4<TX, NTY>(yr + c, o);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (c + j >= w0 && c + j < cend) yr[c + j] = (TX)acc[r][j];
+            }
+        }
+    };
+    for (int64_t c = cb + 4 * (int64_t)threadIdx.x; c < cend; c += 4 * BS) {
+        if (c + 4 <= w0) continue;
+        if (c >= w0 && c + 4 <= cend) chunk(std::true_type{}, c);
+        else chunk(std::false_type{}, c);
+    }
+}
+
+// Band pass of the two-pass transposed schedule: y += (H_up (x) 1) x over
+// column bands, band-major, four columns per thread.  The partner row segments
+// of the band in flight stay in the last-level cache; y is read and written
+// non-temporally so it does not evict them.
+template <typename TX, typename TA, int RB, int BS>
+__global__ __launch_bounds__(BS) void k_upb(ApplyArgs<TX, TA> a, int64_t band, int rw) {
+    using V = typename V4<TX>::t;
+    const int64_t ddn = a.ddn;
+    const int64_t G = (a.dup + rw - 1) / rw;
+    const int64_t bi = blockIdx.x / G;
+    const int64_t g = blockIdx.x - bi * G;
+    const int64_t u0 = g * rw;
+    const int nr = (int)((a.dup - u0) < rw ? (a.dup - u0) : rw);
+    const int64_t c = bi * band + 4 * (int64_t)threadIdx.x;
+    if (4 * (int64_t)threadIdx.x >= band || c >= ddn) return;
+    const bool full = c + 4 <= ddn;
+    for (int r0 = 0; r0 < nr; r0 += RB) {
+        TA acc[RB][4];
+        int64_t u[RB];
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+            u[rr] = u0 + r0 + rr;
+            const bool ok = r0 + rr < nr;
+            if (ok && full) {
+                const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.y + u[rr] * ddn + c));
+                acc[rr][0] = (TA)v.x; acc[rr][1] = (TA)v.y; acc[rr][2] = (TA)v.z; acc[rr][3] = (TA)v.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[rr][j] = (ok && c + j < ddn) ? (TA)a.y[u[rr] * ddn + c + j] : (TA)0;
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+            if (r0 + rr >= nr) break;
+            const int32_t hb = a.up_off[u[rr]], he = a.up_off[u[rr] + 1];
+            int32_t e = hb;
+            if (full) {
+                for (; e + 4 <= he; e += 4) {
+                    V v[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = ld4(a.x + (int64_t)a.up_tgt[e + i] * ddn + c);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const TA am = a.up_sa[e + i];
+                        acc[rr][0] += am * (TA)v[i].x;
+                        acc[rr][1] += am * (TA)v[i].y;
+                        acc[rr][2] += am * (TA)v[i].z;
+                        acc[rr][3] += am * (TA)v[i].w;
+                    }
+                }
+                for (; e < he; ++e) {
+                    const V v = ld4(a.x + (int64_t)a.up_tgt[e] * ddn + c);
+                    const TA am = a.up_sa[e];
+                    acc[rr][0] += am * (TA)v.x;
+                    acc[rr][1] += am * (TA)v.y;
+                    acc[rr][2] += am * (TA)v.z;
+                    acc[rr][3] += am * (TA)v.w;
+                }
+            } else {
+                for (; e < he; ++e) {
+                    const TX *row = a.x + (int64_t)a.up_tgt[e] * ddn;
+                    const TA am = a.up_sa[e];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (c + j < ddn) acc[rr][j] += am * (TA)row[c + j];
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+            if (r0 + rr >= nr) break;
+            TX *yr = a.y + u[rr] * ddn;
+            if (full) {
+                V o;
+                o.x = (TX)acc[rr][0]; o.y = (TX)acc[rr][1]; o.z = (TX)acc[rr][2]; o.w = (TX)acc[rr][3];
+                st4<TX, true>(yr + c, o);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (c + j < ddn) yr[c + j] = (TX)acc[rr][j];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------- variant table --
 // kind 0: single pass.  kind 1: two passes (row-local, then banded up spin).
 struct Variant {
     int kind, R, BS;
     int64_t band;
     const char *name;
+    int64_t wcap;  // kinds 6, 7, 9, 10: cap on the staged window (0 = LDS limit)
+    int rw;        // kind 7: rows per workgroup of the band pass
 };
 static const Variant kVariants[] = {
     {0, 1, 256, 0, "rw_r1_b256"},          {0, 2, 256, 0, "rw_r2_b256"},
@@ -588,6 +1031,29 @@ static const Variant kVariants[] = {
     {5, 8, 256, 512, "tppk_r8_band512"},   {5, 16, 256, 512, "tppk_r16_band512"},
     {4, 4, 512, 4096, "rwpk_r4_b512_w4k"},  {4, 8, 512, 2048, "rwpk_r8_b512_w2k"},
     {4, 4, 1024, 0, "rwpk_r4_b1024"},       {4, 2, 512, 4096, "rwpk_r2_b512_w4k"},
+    // transposed row tiles, single pass (kind 6) and row pass + band pass (kind 7)
+    {6, 1, 256, 0, "rt_r1_b256"},           {6, 2, 256, 0, "rt_r2_b256"},
+    {6, 2, 512, 0, "rt_r2_b512"},           {6, 4, 256, 0, "rt_r4_b256"},
+    {6, 4, 512, 0, "rt_r4_b512"},           {6, 1, 512, 0, "rt_r1_b512"},
+    {7, 1, 256, 256, "rt2_r1_b256_band256", 0, 8},
+    {7, 1, 256, 512, "rt2_r1_b256_band512", 0, 8},
+    {7, 1, 256, 256, "rt2_r1_b256_w12k_band256", 12288, 8},
+    {7, 2, 256, 256, "rt2_r2_b256_w6k_band256", 6144, 8},
+    {7, 1, 256, 1024, "rt2_r1_b256_w12k_band1024", 12288, 16},
+    {7, 2, 512, 256, "rt2_r2_b512_band256", 0, 4},
+    // column-stationary row pass (with the four-fermion terms) + band pass
+    {8, 2, 512, 256, "csx_rr2_rw32_band256", 0, 8},
+    {8, 2, 512, 512, "csx_rr2_rw32_band512", 0, 8},
+    {8, 4, 512, 256, "csx_rr4_rw32_band256", 0, 8},
+    // transposed row tiles over the bond-ordered hop table
+    {9, 1, 256, 0, "rtb_r1_b256"},          {9, 2, 256, 0, "rtb_r2_b256"},
+    {9, 2, 512, 0, "rtb_r2_b512"},          {9, 1, 512, 0, "rtb_r1_b512"},
+    {9, 4, 256, 0, "rtb_r4_b256"},
+    // transposed row tiles aligned to the four-fermion row groups
+    {10, 4, 256, 0, "rtg_r4_b256"},         {10, 4, 512, 0, "rtg_r4_b512"},
+    {10, 4, 256, 0, "rtg_r4_b256_w4k", 4096},
+    {10, 4, 512, 0, "rtg_r4_b512_w4k", 4096},
+    {10, 4, 1024, 0, "rtg_r4_b1024"},       {10, 2, 512, 0, "rtg_r2_b512"},
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static constexpr int64_t kDynBudget = 163840 - 8192;  // LDS left for the staged x block
@@ -679,6 +1145,11 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.dn_sa = Dn.sa64.as<double>();
     a.nmv_dn = Dn.nmv;
     a.dn_ell_pk = Dn.ell_pk.as<uint32_t>();
+    a.dn_ell4_off = Dn.ell4_off.as<int32_t>();
+    a.dn_ell4 = Dn.ell4.as<uint4>();
+    a.nbond = Dn.nbond;
+    a.dn_ell4b = Dn.ell4b.as<uint4>();
+    a.dn_bamp = Dn.bamp64.as<double>();
     a.amp_tab = Dn.amp64.as<double>();
     a.namp = Dn.namp;
     a.dn_e = Dn.ediag64.as<double>();
@@ -699,6 +1170,8 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.xl_amp = h->xl_amp64.as<double>();
     a.partials = partials;
     a.theta = theta;
+    a.tiles = nullptr;
+    a.ntiles = 0;
     return a;
 }
 
@@ -726,6 +1199,11 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.dn_sa = Dn.sa32.as<float>();
     a.nmv_dn = Dn.nmv;
     a.dn_ell_pk = Dn.ell_pk.as<uint32_t>();
+    a.dn_ell4_off = Dn.ell4_off.as<int32_t>();
+    a.dn_ell4 = Dn.ell4.as<uint4>();
+    a.nbond = Dn.nbond;
+    a.dn_ell4b = Dn.ell4b.as<uint4>();
+    a.dn_bamp = Dn.bamp32.as<float>();
     a.amp_tab = Dn.amp32.as<float>();
     a.namp = Dn.namp;
     a.dn_e = Dn.ediag32.as<float>();
@@ -746,6 +1224,8 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.xl_amp = h->xl_amp32.as<float>();
     a.partials = partials;
     a.theta = theta;
+    a.tiles = nullptr;
+    a.ntiles = 0;
     return a;
 }
 
@@ -763,12 +1243,13 @@ ApplyArgs<float, double> make_args<float, double>(const ed_ham_s *h, const void 
 
 template <class K>
 static void allow_lds(K kern) {
-    static bool done = false;
-    if (!done) {
-        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 163840 - 8192);
-        (void)hipGetLastError();
-        done = true;
-    }
+    static std::vector<const void *> done;
+    const void *f = (const void *)kern;
+    for (const void *d : done)
+        if (d == f) return;
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 163840 - 8192);
+    (void)hipGetLastError();
+    done.push_back(f);
 }
 
 template <typename TX, typename TA, int R, int BS, int MODE, bool UPX, bool PK = false>
@@ -798,6 +1279,105 @@ static void launch_band(const ApplyArgs<TX, TA> &a, int64_t band, hipStream_t s)
     ED_LAUNCH_CHECK();
 }
 
+// Row tiles of at most R rows that never split a group of rows joined by the
+// up-spin moves of the four-fermion terms (for moves on the lowest sites such a
+// group is a run of consecutive ranks), so the four-fermion partners of a tile
+// are staged with it.  Groups that are not contiguous or larger than R are cut
+// into plain R-row pieces (their partners are then read from memory).
+static const int2 *tiles_for(ed_ham_s *h, int R, int *ntiles) {
+    for (size_t i = 0; i < h->tiles.size(); ++i)
+        if (h->tiles[i].first == R) {
+            *ntiles = h->tile_counts[i];
+            return h->tiles[i].second ? h->tiles[i].second->as<int2>() : nullptr;
+        }
+    const int64_t dup = h->dup;
+    std::vector<int2> t;
+    if (h->nx > 0 && dup <= (int64_t)1 << 24) {
+        std::vector<int> qs;
+        for (auto &x : h->xterms)
+            if (std::find(qs.begin(), qs.end(), x.up_mv) == qs.end()) qs.push_back(x.up_mv);
+        std::vector<int32_t> par((size_t)dup);
+        for (int64_t u = 0; u < dup; ++u) par[u] = (int32_t)u;
+        auto find = [&](int32_t u) {
+            while (par[u] != u) u = par[u] = par[par[u]];
+            return u;
+        };
+        std::vector<int32_t> mv((size_t)dup);
+        for (int q : qs) {
+            ED_HIP(hipMemcpy(mv.data(), h->sp[0].mv.as<int32_t>() + (size_t)q * dup, (size_t)dup * sizeof(int32_t),
+                             hipMemcpyDeviceToHost));
+            for (int64_t u = 0; u < dup; ++u)
+                if (mv[u] >= 0) {
+                    const int32_t a = find((int32_t)u), b = find(mv[u] >> 1);
+                    if (a != b) par[std::max(a, b)] = std::min(a, b);
+                }
+        }
+        // extent and size of each group, by its root
+        std::vector<int32_t> lo((size_t)dup, INT32_MAX), hi((size_t)dup, -1), cnt((size_t)dup, 0);
+        for (int64_t u = 0; u < dup; ++u) {
+            const int32_t r = find((int32_t)u);
+            lo[r] = std::min(lo[r], (int32_t)u);
+            hi[r] = std::max(hi[r], (int32_t)u);
+            ++cnt[r];
+        }
+        int64_t u = 0, start = 0;
+        while (u < dup) {
+            const int32_t r = find((int32_t)u);
+            int64_t len = 1;
+            if (lo[r] == u && hi[r] - lo[r] + 1 == cnt[r] && cnt[r] <= R) len = cnt[r];
+            if (u + len - start > R) {
+                t.push_back(make_int2((int)start, (int)(u - start)));
+                start = u;
+            }
+            u += len;
+        }
+        t.push_back(make_int2((int)start, (int)(u - start)));
+    }
+    DevMem *m = nullptr;
+    if (!t.empty()) {
+        m = new DevMem();
+        m->alloc(t.size() * sizeof(int2));
+        ED_HIP(hipMemcpy(m->p, t.data(), t.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
+    h->tiles.push_back({R, m});
+    h->tile_counts.push_back((int)t.size());
+    *ntiles = (int)t.size();
+    return m ? m->as<int2>() : nullptr;
+}
+
+template <typename TX, typename TA, int R, int BS, bool UPX, bool BOND = false>
+static void launch_rt(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t wcap, bool grouped = false) {
+    int nwin = 0, wmax = 0;
+    const int64_t amp_bytes = BOND ? 16 : (int64_t)h->sp[1].namp * (int64_t)sizeof(TA) + 16;
+    int64_t cap = (kDynBudget - amp_bytes) / (int64_t)(R * sizeof(TX));
+    if (wcap > 0 && wcap < cap) cap = wcap;
+    a.win = windows_for(h, cap, &nwin, &wmax);
+    a.nwin = nwin;
+    a.wmax = wmax;
+    int ntiles = 0;
+    a.tiles = grouped ? tiles_for(h, R, &ntiles) : nullptr;
+    a.ntiles = ntiles;
+    const int64_t G = a.tiles ? (int64_t)ntiles : (a.dup + R - 1) / R;
+    const size_t shm = (((size_t)R * (size_t)wmax * sizeof(TX) + 15) & ~(size_t)15) + (size_t)amp_bytes;
+    auto kern = k_rt<TX, TA, R, BS, UPX, true, BOND>;
+    allow_lds(kern);
+    kern<<<(unsigned)(G * nwin), BS, shm, s>>>(a);
+    ED_LAUNCH_CHECK();
+}
+
+template <typename TX, typename TA>
+static void launch_upb(const ApplyArgs<TX, TA> &a, int64_t band, int rw, hipStream_t s) {
+    constexpr int RB = 2;
+    const int bs = (int)(band / 4);
+    const int64_t G = (a.dup + rw - 1) / rw;
+    const int64_t nb = (a.ddn + band - 1) / band;
+    if (bs == 64) k_upb<TX, TA, RB, 64><<<(unsigned)(G * nb), 64, 0, s>>>(a, band, rw);
+    else if (bs == 128) k_upb<TX, TA, RB, 128><<<(unsigned)(G * nb), 128, 0, s>>>(a, band, rw);
+    else if (bs == 256) k_upb<TX, TA, RB, 256><<<(unsigned)(G * nb), 256, 0, s>>>(a, band, rw);
+    else fail(ED_EINVAL, "band pass: unsupported band %lld", (long long)band);
+    ED_LAUNCH_CHECK();
+}
+
 // register-tile sizes of the column-stationary kernels
 static int cs_kmax(const ed_ham_s *h) {
     const int m = std::max(h->sp[0].max_hops, h->sp[1].max_hops);
@@ -811,7 +1391,7 @@ static int cs_xmax(const ed_ham_s *h) {
     return h->xl_max <= 4 ? 4 : (h->xl_max <= 8 ? 8 : 0);
 }
 
-template <typename TX, typename TA, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX>
+template <typename TX, typename TA, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX, bool XROW>
 static int64_t launch_cs_k(ed_ham_s *h, ApplyArgs<TX, TA> a, int rw, hipStream_t s) {
     constexpr int BS = 512;
     int nwin = 0, wmax = 0;
@@ -820,26 +1400,26 @@ static int64_t launch_cs_k(ed_ham_s *h, ApplyArgs<TX, TA> a, int rw, hipStream_t
     a.wmax = wmax;
     const int64_t G = (a.dup + rw - 1) / rw;
     const size_t shm = 2 * (size_t)RR * (size_t)wmax * sizeof(TX);
-    k_cs<TX, TA, BS, RR, KMAX, NMV, XMAX, MODE, UPX><<<(unsigned)(G * nwin), BS, shm, s>>>(a, rw);
+    k_cs<TX, TA, BS, RR, KMAX, NMV, XMAX, MODE, UPX, XROW><<<(unsigned)(G * nwin), BS, shm, s>>>(a, rw);
     ED_LAUNCH_CHECK();
     return G * nwin;
 }
 
-template <typename TX, typename TA, int RR, int MODE, bool UPX, int KMAX>
+template <typename TX, typename TA, int RR, int MODE, bool UPX, int KMAX, bool XROW>
 static int64_t launch_cs_km(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
     const int nm = cs_nmv(h), xm = cs_xmax(h);
-    if (nm == 0) return launch_cs_k<TX, TA, RR, KMAX, 0, 0, MODE, UPX>(h, a, rw, s);
-    if (nm == 8 && xm == 4) return launch_cs_k<TX, TA, RR, KMAX, 8, 4, MODE, UPX>(h, a, rw, s);
-    if (nm == 8 && xm == 8) return launch_cs_k<TX, TA, RR, KMAX, 8, 8, MODE, UPX>(h, a, rw, s);
+    if (nm == 0) return launch_cs_k<TX, TA, RR, KMAX, 0, 0, MODE, UPX, XROW>(h, a, rw, s);
+    if (nm == 8 && xm == 4) return launch_cs_k<TX, TA, RR, KMAX, 8, 4, MODE, UPX, XROW>(h, a, rw, s);
+    if (nm == 8 && xm == 8) return launch_cs_k<TX, TA, RR, KMAX, 8, 8, MODE, UPX, XROW>(h, a, rw, s);
     fail(ED_EINVAL, "column-stationary schedule does not fit this Hamiltonian");
 }
 
-template <typename TX, typename TA, int RR, int MODE, bool UPX>
+template <typename TX, typename TA, int RR, int MODE, bool UPX, bool XROW = false>
 static int64_t launch_cs(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
     const int km = cs_kmax(h);
-    if (km == 8) return launch_cs_km<TX, TA, RR, MODE, UPX, 8>(h, a, rw, s);
-    if (km == 16) return launch_cs_km<TX, TA, RR, MODE, UPX, 16>(h, a, rw, s);
-    if (km == 32) return launch_cs_km<TX, TA, RR, MODE, UPX, 32>(h, a, rw, s);
+    if (km == 8) return launch_cs_km<TX, TA, RR, MODE, UPX, 8, XROW>(h, a, rw, s);
+    if (km == 16) return launch_cs_km<TX, TA, RR, MODE, UPX, 16, XROW>(h, a, rw, s);
+    if (km == 32) return launch_cs_km<TX, TA, RR, MODE, UPX, 32, XROW>(h, a, rw, s);
     fail(ED_EINVAL, "column-stationary schedule does not fit this Hamiltonian");
 }
 
@@ -897,6 +1477,32 @@ static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipSt
         case 23: launch_rw<TX, TA, 8, 512, 0, true, true>(h, a, s, V.band); break;
         case 24: launch_rw<TX, TA, 4, 1024, 0, true, true>(h, a, s); break;
         case 25: launch_rw<TX, TA, 2, 512, 0, true, true>(h, a, s, V.band); break;
+        case 26: launch_rt<TX, TA, 1, 256, true>(h, a, s, V.wcap); break;
+        case 27: launch_rt<TX, TA, 2, 256, true>(h, a, s, V.wcap); break;
+        case 28: launch_rt<TX, TA, 2, 512, true>(h, a, s, V.wcap); break;
+        case 29: launch_rt<TX, TA, 4, 256, true>(h, a, s, V.wcap); break;
+        case 30: launch_rt<TX, TA, 4, 512, true>(h, a, s, V.wcap); break;
+        case 31: launch_rt<TX, TA, 1, 512, true>(h, a, s, V.wcap); break;
+        case 32:
+        case 33:
+        case 34:
+        case 36: launch_rt<TX, TA, 1, 256, false>(h, a, s, V.wcap); launch_upb(a, V.band, V.rw, s); break;
+        case 35: launch_rt<TX, TA, 2, 256, false>(h, a, s, V.wcap); launch_upb(a, V.band, V.rw, s); break;
+        case 37: launch_rt<TX, TA, 2, 512, false>(h, a, s, V.wcap); launch_upb(a, V.band, V.rw, s); break;
+        case 38:
+        case 39: launch_cs<TX, TA, 2, 0, false, true>(h, a, 32, s); launch_upb(a, V.band, V.rw, s); break;
+        case 40: launch_cs<TX, TA, 4, 0, false, true>(h, a, 32, s); launch_upb(a, V.band, V.rw, s); break;
+        case 41: launch_rt<TX, TA, 1, 256, true, true>(h, a, s, V.wcap); break;
+        case 42: launch_rt<TX, TA, 2, 256, true, true>(h, a, s, V.wcap); break;
+        case 43: launch_rt<TX, TA, 2, 512, true, true>(h, a, s, V.wcap); break;
+        case 44: launch_rt<TX, TA, 1, 512, true, true>(h, a, s, V.wcap); break;
+        case 45: launch_rt<TX, TA, 4, 256, true, true>(h, a, s, V.wcap); break;
+        case 46:
+        case 48: launch_rt<TX, TA, 4, 256, true>(h, a, s, V.wcap, true); break;
+        case 47:
+        case 49: launch_rt<TX, TA, 4, 512, true>(h, a, s, V.wcap, true); break;
+        case 50: launch_rt<TX, TA, 4, 1024, true>(h, a, s, V.wcap, true); break;
+        case 51: launch_rt<TX, TA, 2, 512, true>(h, a, s, V.wcap, true); break;
         default: fail(ED_EINVAL, "bad apply variant %d", v);
     }
 }
@@ -907,9 +1513,18 @@ static bool variant_fits(const ed_ham_s *h, int v, size_t elem) {
     if ((V.kind == 1 || V.kind == 3) && h->nx == 0 && h->sp[0].nnz == 0) return false;  // no second pass
     if ((V.kind == 2 || V.kind == 3) && (cs_kmax(h) == 0 || cs_nmv(h) < 0 || (h->nx > 0 && cs_xmax(h) == 0)))
         return false;
-    if (V.kind >= 4 && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->sp[1].nmv > 8))
+    if ((V.kind == 4 || V.kind == 5) && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->sp[1].nmv > 8))
         return false;
     if (V.kind == 5 && h->nx == 0 && h->sp[0].nnz == 0) return false;
+    if ((V.kind == 6 || V.kind == 7) && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16))
+        return false;
+    if (V.kind == 7 && h->sp[0].nnz == 0) return false;
+    if (V.kind == 10 && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->nx == 0))
+        return false;
+    if (V.kind == 9 && (h->sp[1].nbond == 0 || !h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16))
+        return false;
+    if (V.kind == 8 && (h->sp[0].nnz == 0 || cs_kmax(h) == 0 || cs_nmv(h) < 0 || (h->nx > 0 && cs_xmax(h) == 0)))
+        return false;
     return true;
 }
 

@@ -15,6 +15,7 @@ import os
 import sys
 from collections import defaultdict
 
+APPLY_KERNELS = ("k_apply", "k_cs<", "k_csb<")
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -57,7 +58,7 @@ def traffic(fetch_csv, write_csv, info_json, workload):
         v = _per_dispatch(path, counter)
         copy = [x for n, l in v.items() if "copy" in n.lower() or "elementwise" in n.lower() for x in l]
         copy = sorted(copy)[-steps:]
-        apply_names = [n for n in v if "k_apply" in n]
+        apply_names = [n for n in v if any(k in n for k in APPLY_KERNELS)]
         # the last `steps` dispatches of each apply kernel are the timed ones
         per_launch = 0.0
         for n in apply_names:
