@@ -398,8 +398,7 @@ __device__ __forceinline__ TA x_sum(const ApplyArgs<TX, TA> &a, const int32_t (&
     return s;
 }
 
-template <typename TX, typename TA, int BS, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX,
-          bool XROW = false>
+template <typename TX, typename TA, int BS, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX>
 __global__ __launch_bounds__(BS) void k_cs(ApplyArgs<TX, TA> a, int rw) {
     // RR rows are processed per step (all their gathers in flight together);
     // LDS holds two buffers of RR row windows.
@@ -483,15 +482,6 @@ __global__ __launch_bounds__(BS) void k_cs(ApplyArgs<TX, TA> a, int rw) {
                     const int32_t xb = r < nr ? a.xl_off[u] : 0, xe = r < nr ? a.xl_off[u + 1] : 0;
                     acc[rr] += x_sum<TX, TA, NMV, XMAX>(a, mvd, xb, xe, u, d);
                 }
-            }
-        } else if constexpr (XROW && NMV > 0) {
-            // four-fermion terms in the row pass (their partners are nearby rows)
-#pragma unroll
-            for (int rr = 0; rr < RR; ++rr) {
-                const int r = r0 + rr;
-                const int64_t u = u0 + (r < nr ? r : 0);
-                const int32_t xb = r < nr ? a.xl_off[u] : 0, xe = r < nr ? a.xl_off[u + 1] : 0;
-                acc[rr] += x_sum<TX, TA, NMV, XMAX>(a, mvd, xb, xe, u, d);
             }
         }
         if (act) {
@@ -665,11 +655,22 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
     const int64_t t = xcd_remap(blockIdx.x, G * nwin);
     const int64_t g = t / nwin;
     const int wi = (int)(t - g * nwin);
-    int64_t u0 = g * R;
-    int nr = (int)((a.dup - u0) < R ? (a.dup - u0) : R);
+    // rank of the row in each slot of the tile (unused slots repeat slot 0)
+    int32_t ur[R];
+    int nr = 0;
     if (a.tiles) {
-        u0 = a.tiles[g].x;
-        nr = a.tiles[g].y;
+        const int4 tq = a.tiles[g];
+        const int32_t tv[4] = {tq.x, tq.y, tq.z, tq.w};
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            ur[r] = tv[r] >= 0 ? tv[r] : tv[0];
+            nr += tv[r] >= 0 ? 1 : 0;
+        }
+    } else {
+        const int64_t u0 = g * R;
+        nr = (int)((a.dup - u0) < R ? (a.dup - u0) : R);
+#pragma unroll
+        for (int r = 0; r < R; ++r) ur[r] = (int32_t)(u0 + (r < nr ? r : 0));
     }
     const int32_t w0 = a.win[wi].x, wl = a.win[wi].y;
     const int64_t cb = (int64_t)(w0 & ~255), cend = (int64_t)w0 + wl;
@@ -680,7 +681,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const bool ok = r < nr;
-        const int64_t u = u0 + (ok ? r : 0);
+        const int64_t u = ur[r];
         eu[r] = ok ? a.up_e[u] : (TA)0;
         su[r] = ok ? a.up_st[u] : 0u;
         cu[r] = ok ? a.up_c[u] : 0u;
@@ -711,7 +712,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 if (r < nr) {
-                    const typename V4<TX>::t q = ld4(a.x + (u0 + r) * ddn + c);
+                    const typename V4<TX>::t q = ld4(a.x + (int64_t)ur[r] * ddn + c);
                     v[r][0] = q.x; v[r][1] = q.y; v[r][2] = q.z; v[r][3] = q.w;
                 }
         } else {
@@ -719,7 +720,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
             for (int r = 0; r < R; ++r)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if (r < nr && c + j >= w0 && c + j < cend) v[r][j] = a.x[(u0 + r) * ddn + c + j];
+                    if (r < nr && c + j >= w0 && c + j < cend) v[r][j] = a.x[(int64_t)ur[r] * ddn + c + j];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -792,7 +793,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
                     } else {
 #pragma unroll
                         for (int r = 0; r < R; ++r)
-                            acc[r][j] += am * (TA)a.x[(u0 + (r < nr ? r : 0)) * ddn + t];
+                            acc[r][j] += am * (TA)a.x[(int64_t)ur[r] * ddn + t];
                     }
                 }
             }
@@ -818,7 +819,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
                     } else {
 #pragma unroll
                         for (int r = 0; r < R; ++r)
-                            acc[r][j] += am * (TA)a.x[(u0 + (r < nr ? r : 0)) * ddn + t];
+                            acc[r][j] += am * (TA)a.x[(int64_t)ur[r] * ddn + t];
                     }
                 }
             }
@@ -854,7 +855,10 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
                         const int k = p[r]++;
                         const int32_t srow = x_src[r][k];
                         const TA am = x_amp[r][k];
-                        const int32_t rs = srow - (int32_t)u0;
+                        int32_t rs = -1;
+#pragma unroll
+                        for (int s2 = 0; s2 < R; ++s2)
+                            if (s2 < nr && ur[s2] == srow) rs = s2;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             const int32_t lc = col[j] - w0;
@@ -904,7 +908,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (r >= nr) break;
-            TX *yr = a.y + (u0 + r) * ddn;
+            TX *yr = a.y + (int64_t)ur[r] * ddn;
             if constexpr (FULL) {
                 V o;
                 o.x = (TX)acc[r][0]; o.y = (TX)acc[r][1]; o.z = (TX)acc[r][2]; o.w = (TX)acc[r][3];
@@ -927,7 +931,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
 // column bands, band-major, four columns per thread.  The partner row segments
 // of the band in flight stay in the last-level cache; y is read and written
 // non-temporally so it does not evict them.
-template <typename TX, typename TA, int RB, int BS>
+template <typename TX, typename TA, int RB, int BS, bool XT = false>
 __global__ __launch_bounds__(BS) void k_upb(ApplyArgs<TX, TA> a, int64_t band, int rw) {
     using V = typename V4<TX>::t;
     const int64_t ddn = a.ddn;
@@ -991,6 +995,50 @@ __global__ __launch_bounds__(BS) void k_upb(ApplyArgs<TX, TA> a, int64_t band, i
                 }
             }
         }
+        if constexpr (XT) {
+            // four-fermion terms; each row's list is ordered by down move, so
+            // a move table entry is loaded once for the RB rows
+            int p[RB], pe[RB];
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+                const bool ok = r0 + rr < nr;
+                p[rr] = ok ? a.xl_off[u[rr]] : 0;
+                pe[rr] = ok ? a.xl_off[u[rr] + 1] : 0;
+            }
+            for (int q = 0; q < a.nmv_dn; ++q) {
+                bool hit = false;
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr) hit |= (p[rr] < pe[rr] && a.xl_tab[p[rr]] == q);
+                if (!hit) continue;
+                int32_t m[4];
+                const int32_t *mp = a.dn_mv + (int64_t)q * ddn + c;
+                if (full) {
+                    int32_t tmp[4];
+                    __builtin_memcpy(tmp, mp, 16);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) m[j] = tmp[j];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) m[j] = c + j < ddn ? mp[j] : -1;
+                }
+                int64_t col[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) col[j] = m[j] >= 0 ? (int64_t)(m[j] >> 1) : (c + j < ddn ? c + j : ddn - 1);
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr) {
+                    while (p[rr] < pe[rr] && a.xl_tab[p[rr]] == q) {
+                        const TX *src = a.x + (int64_t)a.xl_src[p[rr]] * ddn;
+                        const TA am = a.xl_amp[p[rr]];
+                        ++p[rr];
+                        TA v[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) v[j] = (TA)src[col[j]];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) acc[rr][j] += m[j] >= 0 ? ((m[j] & 1) ? -am * v[j] : am * v[j]) : (TA)0;
+                    }
+                }
+            }
+        }
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
             if (r0 + rr >= nr) break;
@@ -1041,7 +1089,7 @@ static const Variant kVariants[] = {
     {7, 2, 256, 256, "rt2_r2_b256_w6k_band256", 6144, 8},
     {7, 1, 256, 1024, "rt2_r1_b256_w12k_band1024", 12288, 16},
     {7, 2, 512, 256, "rt2_r2_b512_band256", 0, 4},
-    // column-stationary row pass (with the four-fermion terms) + band pass
+    // column-stationary row pass + band pass with the four-fermion terms
     {8, 2, 512, 256, "csx_rr2_rw32_band256", 0, 8},
     {8, 2, 512, 512, "csx_rr2_rw32_band512", 0, 8},
     {8, 4, 512, 256, "csx_rr4_rw32_band256", 0, 8},
@@ -1054,6 +1102,12 @@ static const Variant kVariants[] = {
     {10, 4, 256, 0, "rtg_r4_b256_w4k", 4096},
     {10, 4, 512, 0, "rtg_r4_b512_w4k", 4096},
     {10, 4, 1024, 0, "rtg_r4_b1024"},       {10, 2, 512, 0, "rtg_r2_b512"},
+    // packed group tiles: a 4-slot tile holds whole four-fermion row groups
+    // (a group of 3 rows with a single row, ...), rows need not be adjacent
+    {11, 4, 512, 0, "rtp_r4_b512"},         {11, 4, 256, 0, "rtp_r4_b256"},
+    {11, 4, 1024, 0, "rtp_r4_b1024"},
+    {11, 4, 512, 0, "rtp_r4_b512_w4k", 4096}, {11, 4, 256, 0, "rtp_r4_b256_w4k", 4096},
+    {11, 2, 512, 0, "rtp_r2_b512"},
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static constexpr int64_t kDynBudget = 163840 - 8192;  // LDS left for the staged x block
@@ -1279,19 +1333,23 @@ static void launch_band(const ApplyArgs<TX, TA> &a, int64_t band, hipStream_t s)
     ED_LAUNCH_CHECK();
 }
 
-// Row tiles of at most R rows that never split a group of rows joined by the
-// up-spin moves of the four-fermion terms (for moves on the lowest sites such a
-// group is a run of consecutive ranks), so the four-fermion partners of a tile
-// are staged with it.  Groups that are not contiguous or larger than R are cut
-// into plain R-row pieces (their partners are then read from memory).
-static const int2 *tiles_for(ed_ham_s *h, int R, int *ntiles) {
+// Row tiles of at most R rows (R <= 4) that never split a group of rows
+// joined by the up-spin moves of the four-fermion terms, so the four-fermion
+// partners of a tile are staged with it.  A tile lists the rank of the row in
+// each slot (-1 = unused).  packed = false: consecutive groups are packed in
+// order; packed = true: groups are packed best-fit regardless of position (a
+// group of 3 rows with a single row, ...).  Groups that are not runs of
+// consecutive ranks, or larger than R, are cut into runs of at most R rows
+// (their partners are then read from memory).
+static const int4 *tiles_for(ed_ham_s *h, int R, bool packed, int *ntiles) {
+    const int key = R + (packed ? 16 : 0);
     for (size_t i = 0; i < h->tiles.size(); ++i)
-        if (h->tiles[i].first == R) {
+        if (h->tiles[i].first == key) {
             *ntiles = h->tile_counts[i];
-            return h->tiles[i].second ? h->tiles[i].second->as<int2>() : nullptr;
+            return h->tiles[i].second ? h->tiles[i].second->as<int4>() : nullptr;
         }
     const int64_t dup = h->dup;
-    std::vector<int2> t;
+    std::vector<int4> t;
     if (h->nx > 0 && dup <= (int64_t)1 << 24) {
         std::vector<int> qs;
         for (auto &x : h->xterms)
@@ -1312,7 +1370,6 @@ static const int2 *tiles_for(ed_ham_s *h, int R, int *ntiles) {
                     if (a != b) par[std::max(a, b)] = std::min(a, b);
                 }
         }
-        // extent and size of each group, by its root
         std::vector<int32_t> lo((size_t)dup, INT32_MAX), hi((size_t)dup, -1), cnt((size_t)dup, 0);
         for (int64_t u = 0; u < dup; ++u) {
             const int32_t r = find((int32_t)u);
@@ -1320,33 +1377,76 @@ static const int2 *tiles_for(ed_ham_s *h, int R, int *ntiles) {
             hi[r] = std::max(hi[r], (int32_t)u);
             ++cnt[r];
         }
-        int64_t u = 0, start = 0;
-        while (u < dup) {
+        // runs of consecutive ranks, each at most R rows, in rank order
+        std::vector<std::pair<int32_t, int32_t>> runs;  // (first, length)
+        for (int64_t u = 0; u < dup;) {
             const int32_t r = find((int32_t)u);
-            int64_t len = 1;
-            if (lo[r] == u && hi[r] - lo[r] + 1 == cnt[r] && cnt[r] <= R) len = cnt[r];
-            if (u + len - start > R) {
-                t.push_back(make_int2((int)start, (int)(u - start)));
-                start = u;
+            if (lo[r] == u && hi[r] - lo[r] + 1 == cnt[r] && cnt[r] <= R) {
+                runs.push_back({(int32_t)u, cnt[r]});
+                u += cnt[r];
+            } else {
+                runs.push_back({(int32_t)u, 1});
+                u += 1;
             }
-            u += len;
         }
-        t.push_back(make_int2((int)start, (int)(u - start)));
+        auto add = [&](std::vector<int32_t> &slots) {
+            int4 q = make_int4(-1, -1, -1, -1);
+            int32_t *qv = &q.x;
+            for (size_t i = 0; i < slots.size(); ++i) qv[i] = slots[i];
+            t.push_back(q);
+        };
+        if (!packed) {
+            std::vector<int32_t> cur;
+            for (auto &rn : runs) {
+                if ((int)cur.size() + rn.second > R) {
+                    add(cur);
+                    cur.clear();
+                }
+                for (int k = 0; k < rn.second; ++k) cur.push_back(rn.first + k);
+            }
+            if (!cur.empty()) add(cur);
+        } else {
+            // best fit, largest runs first; open tiles kept per free capacity
+            std::vector<std::vector<int32_t>> tl;
+            std::vector<std::vector<int>> open((size_t)R + 1);
+            std::vector<size_t> order(runs.size());
+            for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](size_t x, size_t y) { return runs[x].second > runs[y].second; });
+            for (size_t oi : order) {
+                const int len = runs[oi].second;
+                int ti = -1;
+                for (int cap = len; cap < R && ti < 0; ++cap)
+                    if (!open[cap].empty()) {
+                        ti = open[cap].back();
+                        open[cap].pop_back();
+                    }
+                if (ti < 0) {
+                    ti = (int)tl.size();
+                    tl.emplace_back();
+                }
+                for (int k = 0; k < len; ++k) tl[ti].push_back(runs[oi].first + k);
+                const int fr = R - (int)tl[ti].size();
+                if (fr > 0) open[fr].push_back(ti);
+            }
+            for (auto &v : tl) add(v);
+        }
     }
     DevMem *m = nullptr;
     if (!t.empty()) {
         m = new DevMem();
-        m->alloc(t.size() * sizeof(int2));
-        ED_HIP(hipMemcpy(m->p, t.data(), t.size() * sizeof(int2), hipMemcpyHostToDevice));
+        m->alloc(t.size() * sizeof(int4));
+        ED_HIP(hipMemcpy(m->p, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
     }
-    h->tiles.push_back({R, m});
+    h->tiles.push_back({key, m});
     h->tile_counts.push_back((int)t.size());
     *ntiles = (int)t.size();
-    return m ? m->as<int2>() : nullptr;
+    return m ? m->as<int4>() : nullptr;
 }
 
 template <typename TX, typename TA, int R, int BS, bool UPX, bool BOND = false>
-static void launch_rt(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t wcap, bool grouped = false) {
+static void launch_rt(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t wcap, bool grouped = false,
+                      bool packed = false) {
     int nwin = 0, wmax = 0;
     const int64_t amp_bytes = BOND ? 16 : (int64_t)h->sp[1].namp * (int64_t)sizeof(TA) + 16;
     int64_t cap = (kDynBudget - amp_bytes) / (int64_t)(R * sizeof(TX));
@@ -1355,7 +1455,7 @@ static void launch_rt(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t w
     a.nwin = nwin;
     a.wmax = wmax;
     int ntiles = 0;
-    a.tiles = grouped ? tiles_for(h, R, &ntiles) : nullptr;
+    a.tiles = grouped ? tiles_for(h, R, packed, &ntiles) : nullptr;
     a.ntiles = ntiles;
     const int64_t G = a.tiles ? (int64_t)ntiles : (a.dup + R - 1) / R;
     const size_t shm = (((size_t)R * (size_t)wmax * sizeof(TX) + 15) & ~(size_t)15) + (size_t)amp_bytes;
@@ -1365,15 +1465,15 @@ static void launch_rt(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t w
     ED_LAUNCH_CHECK();
 }
 
-template <typename TX, typename TA>
+template <typename TX, typename TA, bool XT = false>
 static void launch_upb(const ApplyArgs<TX, TA> &a, int64_t band, int rw, hipStream_t s) {
     constexpr int RB = 2;
     const int bs = (int)(band / 4);
     const int64_t G = (a.dup + rw - 1) / rw;
     const int64_t nb = (a.ddn + band - 1) / band;
-    if (bs == 64) k_upb<TX, TA, RB, 64><<<(unsigned)(G * nb), 64, 0, s>>>(a, band, rw);
-    else if (bs == 128) k_upb<TX, TA, RB, 128><<<(unsigned)(G * nb), 128, 0, s>>>(a, band, rw);
-    else if (bs == 256) k_upb<TX, TA, RB, 256><<<(unsigned)(G * nb), 256, 0, s>>>(a, band, rw);
+    if (bs == 64) k_upb<TX, TA, RB, 64, XT><<<(unsigned)(G * nb), 64, 0, s>>>(a, band, rw);
+    else if (bs == 128) k_upb<TX, TA, RB, 128, XT><<<(unsigned)(G * nb), 128, 0, s>>>(a, band, rw);
+    else if (bs == 256) k_upb<TX, TA, RB, 256, XT><<<(unsigned)(G * nb), 256, 0, s>>>(a, band, rw);
     else fail(ED_EINVAL, "band pass: unsupported band %lld", (long long)band);
     ED_LAUNCH_CHECK();
 }
@@ -1391,7 +1491,7 @@ static int cs_xmax(const ed_ham_s *h) {
     return h->xl_max <= 4 ? 4 : (h->xl_max <= 8 ? 8 : 0);
 }
 
-template <typename TX, typename TA, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX, bool XROW>
+template <typename TX, typename TA, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX>
 static int64_t launch_cs_k(ed_ham_s *h, ApplyArgs<TX, TA> a, int rw, hipStream_t s) {
     constexpr int BS = 512;
     int nwin = 0, wmax = 0;
@@ -1400,26 +1500,26 @@ static int64_t launch_cs_k(ed_ham_s *h, ApplyArgs<TX, TA> a, int rw, hipStream_t
     a.wmax = wmax;
     const int64_t G = (a.dup + rw - 1) / rw;
     const size_t shm = 2 * (size_t)RR * (size_t)wmax * sizeof(TX);
-    k_cs<TX, TA, BS, RR, KMAX, NMV, XMAX, MODE, UPX, XROW><<<(unsigned)(G * nwin), BS, shm, s>>>(a, rw);
+    k_cs<TX, TA, BS, RR, KMAX, NMV, XMAX, MODE, UPX><<<(unsigned)(G * nwin), BS, shm, s>>>(a, rw);
     ED_LAUNCH_CHECK();
     return G * nwin;
 }
 
-template <typename TX, typename TA, int RR, int MODE, bool UPX, int KMAX, bool XROW>
+template <typename TX, typename TA, int RR, int MODE, bool UPX, int KMAX>
 static int64_t launch_cs_km(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
     const int nm = cs_nmv(h), xm = cs_xmax(h);
-    if (nm == 0) return launch_cs_k<TX, TA, RR, KMAX, 0, 0, MODE, UPX, XROW>(h, a, rw, s);
-    if (nm == 8 && xm == 4) return launch_cs_k<TX, TA, RR, KMAX, 8, 4, MODE, UPX, XROW>(h, a, rw, s);
-    if (nm == 8 && xm == 8) return launch_cs_k<TX, TA, RR, KMAX, 8, 8, MODE, UPX, XROW>(h, a, rw, s);
+    if (nm == 0) return launch_cs_k<TX, TA, RR, KMAX, 0, 0, MODE, UPX>(h, a, rw, s);
+    if (nm == 8 && xm == 4) return launch_cs_k<TX, TA, RR, KMAX, 8, 4, MODE, UPX>(h, a, rw, s);
+    if (nm == 8 && xm == 8) return launch_cs_k<TX, TA, RR, KMAX, 8, 8, MODE, UPX>(h, a, rw, s);
     fail(ED_EINVAL, "column-stationary schedule does not fit this Hamiltonian");
 }
 
-template <typename TX, typename TA, int RR, int MODE, bool UPX, bool XROW = false>
+template <typename TX, typename TA, int RR, int MODE, bool UPX>
 static int64_t launch_cs(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
     const int km = cs_kmax(h);
-    if (km == 8) return launch_cs_km<TX, TA, RR, MODE, UPX, 8, XROW>(h, a, rw, s);
-    if (km == 16) return launch_cs_km<TX, TA, RR, MODE, UPX, 16, XROW>(h, a, rw, s);
-    if (km == 32) return launch_cs_km<TX, TA, RR, MODE, UPX, 32, XROW>(h, a, rw, s);
+    if (km == 8) return launch_cs_km<TX, TA, RR, MODE, UPX, 8>(h, a, rw, s);
+    if (km == 16) return launch_cs_km<TX, TA, RR, MODE, UPX, 16>(h, a, rw, s);
+    if (km == 32) return launch_cs_km<TX, TA, RR, MODE, UPX, 32>(h, a, rw, s);
     fail(ED_EINVAL, "column-stationary schedule does not fit this Hamiltonian");
 }
 
@@ -1490,8 +1590,8 @@ static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipSt
         case 35: launch_rt<TX, TA, 2, 256, false>(h, a, s, V.wcap); launch_upb(a, V.band, V.rw, s); break;
         case 37: launch_rt<TX, TA, 2, 512, false>(h, a, s, V.wcap); launch_upb(a, V.band, V.rw, s); break;
         case 38:
-        case 39: launch_cs<TX, TA, 2, 0, false, true>(h, a, 32, s); launch_upb(a, V.band, V.rw, s); break;
-        case 40: launch_cs<TX, TA, 4, 0, false, true>(h, a, 32, s); launch_upb(a, V.band, V.rw, s); break;
+        case 39: launch_cs<TX, TA, 2, 0, false>(h, a, 32, s); launch_upb<TX, TA, true>(a, V.band, V.rw, s); break;
+        case 40: launch_cs<TX, TA, 4, 0, false>(h, a, 32, s); launch_upb<TX, TA, true>(a, V.band, V.rw, s); break;
         case 41: launch_rt<TX, TA, 1, 256, true, true>(h, a, s, V.wcap); break;
         case 42: launch_rt<TX, TA, 2, 256, true, true>(h, a, s, V.wcap); break;
         case 43: launch_rt<TX, TA, 2, 512, true, true>(h, a, s, V.wcap); break;
@@ -1503,6 +1603,12 @@ static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipSt
         case 49: launch_rt<TX, TA, 4, 512, true>(h, a, s, V.wcap, true); break;
         case 50: launch_rt<TX, TA, 4, 1024, true>(h, a, s, V.wcap, true); break;
         case 51: launch_rt<TX, TA, 2, 512, true>(h, a, s, V.wcap, true); break;
+        case 52:
+        case 55: launch_rt<TX, TA, 4, 512, true>(h, a, s, V.wcap, true, true); break;
+        case 53:
+        case 56: launch_rt<TX, TA, 4, 256, true>(h, a, s, V.wcap, true, true); break;
+        case 54: launch_rt<TX, TA, 4, 1024, true>(h, a, s, V.wcap, true, true); break;
+        case 57: launch_rt<TX, TA, 2, 512, true>(h, a, s, V.wcap, true, true); break;
         default: fail(ED_EINVAL, "bad apply variant %d", v);
     }
 }
@@ -1519,7 +1625,7 @@ static bool variant_fits(const ed_ham_s *h, int v, size_t elem) {
     if ((V.kind == 6 || V.kind == 7) && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16))
         return false;
     if (V.kind == 7 && h->sp[0].nnz == 0) return false;
-    if (V.kind == 10 && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->nx == 0))
+    if ((V.kind == 10 || V.kind == 11) && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->nx == 0))
         return false;
     if (V.kind == 9 && (h->sp[1].nbond == 0 || !h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16))
         return false;

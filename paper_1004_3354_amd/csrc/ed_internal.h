@@ -198,7 +198,7 @@ struct ed_ham_s {
     std::vector<std::pair<int64_t, ed::DevMem *>> windows;  // (capacity, device int2 list)
     std::vector<int> window_counts;
     // row tiles of at most R rows that keep each group of rows joined by the
-    // four-fermion up-spin moves together: (R, device int2 (first row, rows) list)
+    // four-fermion up-spin moves together: (R + 16 * packed, device int4 slot list)
     std::vector<std::pair<int, ed::DevMem *>> tiles;
     std::vector<int> tile_counts;
     ~ed_ham_s() {
@@ -257,8 +257,9 @@ struct ApplyArgs {
     const int2 *win;
     int nwin;
     int wmax;
-    // row tiles (first row, rows); nullptr = consecutive tiles of R rows
-    const int2 *tiles;
+    // row tiles: rank of the row in each slot (-1 = unused); nullptr =
+    // consecutive tiles of R rows
+    const int4 *tiles;
     int ntiles;
 };
 
