@@ -53,6 +53,18 @@ def traffic_from_profile(workload, schedule):
     return e.get("bytes_per_launch")
 
 
+def schedule_kernels(name):
+    """Kernels one apply launches under a schedule (by schedule-name prefix)."""
+    for pre, k in (("rtg_", "k_rt (group-aligned tiles)"), ("rtp_", "k_rt (packed group tiles)"),
+                   ("rtb_", "k_rt (bond-ordered table)"), ("rt2_", "k_rt row pass + k_upb band pass"),
+                   ("rt_", "k_rt"), ("csx_", "k_cs row pass + k_upb band pass"),
+                   ("cstp_", "k_cs + k_csb"), ("cs_", "k_cs"), ("tppk_", "k_apply + k_apply_band"),
+                   ("tp_", "k_apply + k_apply_band"), ("rwpk_", "k_apply (packed table)"), ("rw_", "k_apply")):
+        if name.startswith(pre):
+            return k
+    return name
+
+
 def timed_applies(H, x, y, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -98,7 +110,7 @@ def cpu_baseline(cfg, target_s=12.0):
     sec.rows_apply(rows, x)
     dt = time.perf_counter() - t0
     n = int(min(sec.D, max(n, n * target_s / max(dt, 1e-6))))
-    rows = np.sort(rng.choice(sec.D, n, replace=False))
+    rows = np.arange(sec.D) if n == sec.D else np.sort(rng.choice(sec.D, n, replace=False))
     t0 = time.perf_counter()
     sec.rows_apply(rows, x)
     dt = time.perf_counter() - t0
@@ -111,8 +123,9 @@ def cpu_baseline(cfg, target_s=12.0):
     rate = n / dt                       # rows (output elements) per second
     return {"value": round(16.0 * rate / 1e9, 4), "unit": "GB/s (FP64 algorithmic: 16 B per output element)",
             "cores": int(threads), "kind": "oracle",
-            "sample": "%d random rows of the N_s=15 sector, literal Jordan-Wigner operator strings per row "
-                      "(matrix-free oracle path), %.1f s" % (n, dt),
+            "sample": ("%s of the N_s=15 sector, literal Jordan-Wigner operator strings per row "
+                       "(matrix-free oracle path), %.1f s"
+                       % ("all %d rows (one full H.v)" % n if n == sec.D else "%d random rows" % n, dt)),
             "rows_per_s": round(rate, 1)}
 
 
@@ -345,7 +358,7 @@ def main():
                    "schedule_id": variant_id},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_apply<float,float> (%s)" % variant,
+                     "kernel": "%s (schedule %s)" % (schedule_kernels(variant), variant),
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": round(kern_s * 1e3, 5)},
         "cpu_baseline": cpu,

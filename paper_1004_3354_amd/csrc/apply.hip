@@ -599,6 +599,19 @@ __device__ __forceinline__ TX rv_get(const typename RV<TX, R>::t &v, int r) {
     if constexpr (R == 1) return v;
     else return v[r];
 }
+// component q of an R-vector by selects (a partner read from the LDS tile is a
+// whole-column vector load, so it is never merged with a scalar memory load of
+// the same value into one generic-address load)
+template <typename TX, int R>
+__device__ __forceinline__ TX rv_pick(const typename RV<TX, R>::t &v, int q) {
+    if constexpr (R == 1) return v;
+    else {
+        TX o = v[0];
+#pragma unroll
+        for (int k = 1; k < R; ++k) o = q == k ? v[k] : o;
+        return o;
+    }
+}
 template <typename TX, bool NT>
 __device__ __forceinline__ void st4(TX *p, typename V4<TX>::t v) {
     if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<typename V4<TX>::t *>(p));
@@ -610,7 +623,7 @@ __device__ __forceinline__ typename V4<TX>::t ld4(const TX *p) {
 }
 
 // cross term with the per-site U values and the 4^koff table taken from LDS
-// copies (xtl is used when koff <= 4)
+// copies (the kernels that use it require koff <= 4)
 template <typename TX, typename TA>
 __device__ __forceinline__ TA cross_term_l(const ApplyArgs<TX, TA> &a, const TA *usl, const TA *xtl, uint32_t su,
                                            uint32_t sd, uint32_t cu, uint32_t cd) {
@@ -624,7 +637,7 @@ __device__ __forceinline__ TA cross_term_l(const ApplyArgs<TX, TA> &a, const TA 
             m &= m - 1u;
         }
     }
-    if (a.koff) c += a.koff <= 4 ? xtl[(cu << a.koff) | cd] : a.xtab[(cu << a.koff) | cd];
+    if (a.koff) c += xtl[(cu << a.koff) | cd];
     return c;
 }
 
@@ -762,8 +775,9 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t l = c + j - w0;
-            RVt v = (RVt)0;
-            if (FULL || (l >= 0 && l < wl)) v = *reinterpret_cast<const RVt *>(xs + l * R);
+            const bool inw = FULL || (l >= 0 && l < wl);
+            RVt v = *reinterpret_cast<const RVt *>(xs + (inw ? l : 0) * R);
+            if (!inw) v = (RVt)0;
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 acc[r][j] = (eu[r] + edn[j] + cross_term_l(a, usl, xtl, su[r], sd[j], cu[r], cd[j])) *
@@ -862,11 +876,18 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             const int32_t lc = col[j] - w0;
+                            // the LDS read is unconditional (clamped index) so that
+                            // it is not merged with the memory read into one
+                            // generic-address load
+                            const bool in = (uint32_t)rs < (uint32_t)nr && (uint32_t)lc < (uint32_t)wl;
                             TA v;
-                            if ((uint32_t)rs < (uint32_t)nr && (uint32_t)lc < (uint32_t)wl)
-                                v = (TA)xs[(int64_t)lc * R + rs];
-                            else
-                                v = (TA)a.x[(int64_t)srow * ddn + col[j]];
+                            if constexpr (R == 1) {
+                                v = (TA)a.x[(int64_t)srow * ddn + col[j]];  // a partner row is never the row itself
+                            } else {
+                                const RVt w = *reinterpret_cast<const RVt *>(xs + (in ? (int64_t)lc : 0) * R);
+                                v = (TA)rv_pick<TX, R>(w, rs);
+                                if (!in) v = (TA)a.x[(int64_t)srow * ddn + col[j]];
+                            }
                             v = m[j] >= 0 ? ((m[j] & 1) ? -v : v) : (TA)0;
                             acc[r][j] += am * v;
                         }
@@ -1622,6 +1643,7 @@ static bool variant_fits(const ed_ham_s *h, int v, size_t elem) {
     if ((V.kind == 4 || V.kind == 5) && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->sp[1].nmv > 8))
         return false;
     if (V.kind == 5 && h->nx == 0 && h->sp[0].nnz == 0) return false;
+    if ((V.kind == 6 || V.kind == 7 || V.kind == 9 || V.kind == 10 || V.kind == 11) && h->koff > 4) return false;
     if ((V.kind == 6 || V.kind == 7) && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16))
         return false;
     if (V.kind == 7 && h->sp[0].nnz == 0) return false;

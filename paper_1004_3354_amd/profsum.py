@@ -15,7 +15,7 @@ import os
 import sys
 from collections import defaultdict
 
-APPLY_KERNELS = ("k_apply", "k_cs<", "k_csb<")
+APPLY_KERNELS = ("k_apply", "k_cs<", "k_csb<", "k_rt<", "k_upb<")
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
