@@ -292,59 +292,6 @@ __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
     }
 }
 
-// Second pass of the two-pass schedule: y += (H_up (x) 1) x + four-fermion
-// terms over column bands.  Blocks run band-major, so while one band is in
-// flight its slice of x (D_up x band) stays in the last-level cache and each
-// partner row segment is fetched from HBM about once instead of once per
-// neighbouring row.  A thread owns one column of RB rows at a time.
-template <typename TX, typename TA, int RB, int BS>
-__global__ __launch_bounds__(BS) void k_apply_band(ApplyArgs<TX, TA> a, int64_t band) {
-    const int64_t ddn = a.ddn;
-    const int64_t G = (a.dup + RB - 1) / RB;
-    const int64_t bi = blockIdx.x / G;
-    const int64_t g = blockIdx.x - bi * G;
-    const int64_t u0 = g * RB;
-    const int nr = (int)((a.dup - u0) < RB ? (a.dup - u0) : RB);
-    const int64_t c0 = bi * band, c1 = (c0 + band < ddn) ? c0 + band : ddn;
-    int32_t hb[RB], he[RB], xb[RB], xe[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        const bool ok = r < nr;
-        const int64_t u = u0 + (ok ? r : 0);
-        hb[r] = ok ? a.up_off[u] : 0;
-        he[r] = ok ? a.up_off[u + 1] : 0;
-        xb[r] = ok ? a.xl_off[u] : 0;
-        xe[r] = ok ? a.xl_off[u + 1] : 0;
-    }
-    for (int64_t d = c0 + threadIdx.x; d < c1; d += BS) {
-        TA acc[RB];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) acc[r] = r < nr ? (TA)a.y[(u0 + r) * ddn + d] : (TA)0;
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            int32_t e = hb[r];
-            for (; e + 4 <= he[r]; e += 4) {
-                const TA v0 = (TA)a.x[(int64_t)a.up_tgt[e] * ddn + d];
-                const TA v1 = (TA)a.x[(int64_t)a.up_tgt[e + 1] * ddn + d];
-                const TA v2 = (TA)a.x[(int64_t)a.up_tgt[e + 2] * ddn + d];
-                const TA v3 = (TA)a.x[(int64_t)a.up_tgt[e + 3] * ddn + d];
-                acc[r] += a.up_sa[e] * v0 + a.up_sa[e + 1] * v1 + a.up_sa[e + 2] * v2 + a.up_sa[e + 3] * v3;
-            }
-            for (; e < he[r]; ++e) acc[r] += a.up_sa[e] * (TA)a.x[(int64_t)a.up_tgt[e] * ddn + d];
-            for (int32_t q = xb[r]; q < xe[r]; ++q) {
-                const int32_t m = a.dn_mv[(int64_t)a.xl_tab[q] * ddn + d];
-                const int64_t c = m >= 0 ? (int64_t)(m >> 1) : d;
-                TA v = (TA)a.x[(int64_t)a.xl_src[q] * ddn + c];
-                v = m >= 0 ? ((m & 1) ? -v : v) : (TA)0;
-                acc[r] += a.xl_amp[q] * v;
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-            if (r < nr) a.y[(u0 + r) * ddn + d] = (TX)acc[r];
-    }
-}
-
 // Column-stationary kernel.  A workgroup owns one window of down ranks (at
 // most BS*CPT of them, a run of states sharing their top bits) and streams over
 // `rw` consecutive rows.  Each thread owns CPT columns and keeps everything
@@ -355,48 +302,6 @@ __global__ __launch_bounds__(BS) void k_apply_band(ApplyArgs<TX, TA> a, int64_t 
 // the four-fermion terms.  Per row only independent gathers remain: the row
 // window (double-buffered in LDS), the up-spin partner rows and the
 // four-fermion partners, so many loads are in flight per wave.
-
-// Up-spin partners of row u at column d, unrolled to UMAX entries (padding
-// entries read the row itself with amplitude 0), so all loads are independent.
-template <typename TX, typename TA, int UMAX>
-__device__ __forceinline__ TA up_sum(const ApplyArgs<TX, TA> &a, int32_t hb, int32_t he, int64_t u, int64_t d) {
-    TA w[UMAX], v[UMAX];
-#pragma unroll
-    for (int k = 0; k < UMAX; ++k) {
-        const bool ok = hb + k < he;
-        const int64_t src = ok ? (int64_t)a.up_tgt[hb + k] : u;
-        w[k] = ok ? a.up_sa[hb + k] : (TA)0;
-        v[k] = (TA)a.x[src * a.ddn + d];
-    }
-    TA s = (TA)0;
-#pragma unroll
-    for (int k = 0; k < UMAX; ++k) s += w[k] * v[k];
-    return s;
-}
-
-// Four-fermion terms allowed on row u at column d, unrolled to XMAX entries.
-template <typename TX, typename TA, int NMV, int XMAX>
-__device__ __forceinline__ TA x_sum(const ApplyArgs<TX, TA> &a, const int32_t (&mvd)[NMV > 0 ? NMV : 1],
-                                    int32_t xb, int32_t xe, int64_t u, int64_t d) {
-    TA w[XMAX > 0 ? XMAX : 1], v[XMAX > 0 ? XMAX : 1];
-    int32_t mm[XMAX > 0 ? XMAX : 1];
-#pragma unroll
-    for (int k = 0; k < XMAX; ++k) {
-        const bool ok = xb + k < xe;
-        const int32_t m = ok ? pick<NMV>(mvd, a.xl_tab[xb + k]) : -1;
-        const int64_t src = ok ? (int64_t)a.xl_src[xb + k] : u;
-        w[k] = ok ? a.xl_amp[xb + k] : (TA)0;
-        mm[k] = m;
-        v[k] = (TA)a.x[src * a.ddn + (m >= 0 ? (int64_t)(m >> 1) : d)];
-    }
-    TA s = (TA)0;
-#pragma unroll
-    for (int k = 0; k < XMAX; ++k) {
-        const TA t = mm[k] >= 0 ? ((mm[k] & 1) ? -v[k] : v[k]) : (TA)0;
-        s += w[k] * t;
-    }
-    return s;
-}
 
 template <typename TX, typename TA, int BS, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX>
 __global__ __launch_bounds__(BS) void k_cs(ApplyArgs<TX, TA> a, int rw) {
@@ -471,19 +376,6 @@ __global__ __launch_bounds__(BS) void k_cs(ApplyArgs<TX, TA> a, int rw) {
                 acc[rr] += sa[k] * v;
             }
         }
-        if constexpr (UPX) {
-#pragma unroll
-            for (int rr = 0; rr < RR; ++rr) {
-                const int r = r0 + rr;
-                const int64_t u = u0 + (r < nr ? r : 0);
-                const int32_t hb = r < nr ? a.up_off[u] : 0, he = r < nr ? a.up_off[u + 1] : 0;
-                acc[rr] += up_sum<TX, TA, KMAX>(a, hb, he, u, d);
-                if constexpr (NMV > 0) {
-                    const int32_t xb = r < nr ? a.xl_off[u] : 0, xe = r < nr ? a.xl_off[u + 1] : 0;
-                    acc[rr] += x_sum<TX, TA, NMV, XMAX>(a, mvd, xb, xe, u, d);
-                }
-            }
-        }
         if (act) {
 #pragma unroll
             for (int rr = 0; rr < RR; ++rr) {
@@ -510,62 +402,6 @@ __global__ __launch_bounds__(BS) void k_cs(ApplyArgs<TX, TA> a, int rw) {
         if (threadIdx.x == 0) {
             a.partials[2 * (int64_t)blockIdx.x] = s0;
             a.partials[2 * (int64_t)blockIdx.x + 1] = s1;
-        }
-    }
-}
-
-// Column-stationary second pass over column bands (band-major): y += up-spin
-// term + four-fermion terms, each thread owning one column of the band and
-// streaming over `rw` rows.
-template <typename TX, typename TA, int BS, int RR, int UMAX, int NMV, int XMAX>
-__global__ __launch_bounds__(BS) void k_csb(ApplyArgs<TX, TA> a, int64_t band, int rw) {
-    const int64_t ddn = a.ddn;
-    const int64_t G = (a.dup + rw - 1) / rw;
-    const int64_t bi = blockIdx.x / G;
-    const int64_t g = blockIdx.x - bi * G;
-    const int64_t u0 = g * rw;
-    const int nr = (int)((a.dup - u0) < rw ? (a.dup - u0) : rw);
-    const int64_t d = bi * band + threadIdx.x;
-    if (threadIdx.x >= band || d >= ddn) return;
-    int32_t mvd[NMV > 0 ? NMV : 1];
-#pragma unroll
-    for (int q = 0; q < NMV; ++q) mvd[q] = q < a.nmv_dn ? a.dn_mv[(int64_t)q * ddn + d] : -1;
-    for (int r0 = 0; r0 < nr; r0 += RR) {
-        TA acc[RR];
-#pragma unroll
-        for (int rr = 0; rr < RR; ++rr) {
-            const int r = r0 + rr;
-            acc[rr] = r < nr ? (TA)a.y[(u0 + r) * ddn + d] : (TA)0;
-        }
-#pragma unroll
-        for (int rr = 0; rr < RR; ++rr) {
-            const int r = r0 + rr;
-            const int64_t u = u0 + (r < nr ? r : 0);
-            const int32_t hb = r < nr ? a.up_off[u] : 0, he = r < nr ? a.up_off[u + 1] : 0;
-            int32_t e = hb;
-            for (; e + 4 <= he; e += 4) {
-                const TA v0 = (TA)a.x[(int64_t)a.up_tgt[e] * ddn + d];
-                const TA v1 = (TA)a.x[(int64_t)a.up_tgt[e + 1] * ddn + d];
-                const TA v2 = (TA)a.x[(int64_t)a.up_tgt[e + 2] * ddn + d];
-                const TA v3 = (TA)a.x[(int64_t)a.up_tgt[e + 3] * ddn + d];
-                acc[rr] += a.up_sa[e] * v0 + a.up_sa[e + 1] * v1 + a.up_sa[e + 2] * v2 + a.up_sa[e + 3] * v3;
-            }
-            for (; e < he; ++e) acc[rr] += a.up_sa[e] * (TA)a.x[(int64_t)a.up_tgt[e] * ddn + d];
-            if constexpr (NMV > 0) {
-                const int32_t xb = r < nr ? a.xl_off[u] : 0, xe = r < nr ? a.xl_off[u + 1] : 0;
-                for (int32_t q = xb; q < xe; ++q) {
-                    const int32_t m = pick<NMV>(mvd, a.xl_tab[q]);
-                    const int64_t cc = m >= 0 ? (int64_t)(m >> 1) : d;
-                    TA v = (TA)a.x[(int64_t)a.xl_src[q] * ddn + cc];
-                    v = m >= 0 ? ((m & 1) ? -v : v) : (TA)0;
-                    acc[rr] += a.xl_amp[q] * v;
-                }
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < RR; ++rr) {
-            const int r = r0 + rr;
-            if (r < nr) a.y[(u0 + r) * ddn + d] = (TX)acc[rr];
         }
     }
 }
@@ -641,7 +477,7 @@ __device__ __forceinline__ TA cross_term_l(const ApplyArgs<TX, TA> &a, const TA 
     return c;
 }
 
-template <typename TX, typename TA, int R, int BS, bool UPX, bool NTY, bool BOND = false>
+template <typename TX, typename TA, int R, int BS, bool UPX, bool NTY>
 __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
     using RVt = typename RV<TX, R>::t;
     using V = typename V4<TX>::t;
@@ -654,9 +490,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
     __shared__ int32_t x_src[R][XL], x_tab[R][XL];
     __shared__ TA x_amp[R][XL];
     __shared__ TA usl[32], xtl[256];
-    if constexpr (!BOND) {
-        for (int k = threadIdx.x; k < a.namp; k += BS) amps[k] = a.amp_tab[k];
-    }
+    for (int k = threadIdx.x; k < a.namp; k += BS) amps[k] = a.amp_tab[k];
     if (a.umode == 2)
         for (int k = threadIdx.x; k < 32; k += BS) usl[k] = a.usite[k];
     if (a.koff && a.koff <= 4)
@@ -664,27 +498,16 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
 
     const int64_t ddn = a.ddn;
     const int nwin = a.nwin;
-    const int64_t G = a.tiles ? (int64_t)a.ntiles : (a.dup + R - 1) / R;
+    const int64_t G = (a.dup + R - 1) / R;
     const int64_t t = xcd_remap(blockIdx.x, G * nwin);
     const int64_t g = t / nwin;
     const int wi = (int)(t - g * nwin);
     // rank of the row in each slot of the tile (unused slots repeat slot 0)
     int32_t ur[R];
-    int nr = 0;
-    if (a.tiles) {
-        const int4 tq = a.tiles[g];
-        const int32_t tv[4] = {tq.x, tq.y, tq.z, tq.w};
+    const int64_t u0 = g * R;
+    const int nr = (int)((a.dup - u0) < R ? (a.dup - u0) : R);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            ur[r] = tv[r] >= 0 ? tv[r] : tv[0];
-            nr += tv[r] >= 0 ? 1 : 0;
-        }
-    } else {
-        const int64_t u0 = g * R;
-        nr = (int)((a.dup - u0) < R ? (a.dup - u0) : R);
-#pragma unroll
-        for (int r = 0; r < R; ++r) ur[r] = (int32_t)(u0 + (r < nr ? r : 0));
-    }
+    for (int r = 0; r < R; ++r) ur[r] = (int32_t)(u0 + (r < nr ? r : 0));
     const int32_t w0 = a.win[wi].x, wl = a.win[wi].y;
     const int64_t cb = (int64_t)(w0 & ~255), cend = (int64_t)w0 + wl;
 
@@ -784,34 +607,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
                             (TA)rv_get<TX, R>(v, r);
         }
         // 1 (x) H_dn
-        if constexpr (BOND) {
-            // slot k is bond k for every state: uniform amplitude, sign and
-            // activity from the entry
-            const int lane = threadIdx.x & 63;
-            const int nb = a.nbond;
-            const uint4 *ep = a.dn_ell4b + ((c >> 8) * nb) * 64 + lane;
-#pragma unroll 2
-            for (int k = 0; k < nb; ++k) {
-                const uint4 e = ep[(int64_t)k * 64];
-                const TA hk = a.dn_bamp[k];
-                const uint32_t ev[4] = {e.x, e.y, e.z, e.w};
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int32_t t = (int32_t)(ev[j] & 0xFFFFFu);
-                    const TA am = (ev[j] & (1u << 21)) ? ((ev[j] & (1u << 20)) ? -hk : hk) : (TA)0;
-                    const int32_t l = t - w0;
-                    if ((uint32_t)l < (uint32_t)wl) {
-                        const RVt v = *reinterpret_cast<const RVt *>(xs + (int64_t)l * R);
-#pragma unroll
-                        for (int r = 0; r < R; ++r) acc[r][j] += am * (TA)rv_get<TX, R>(v, r);
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < R; ++r)
-                            acc[r][j] += am * (TA)a.x[(int64_t)ur[r] * ddn + t];
-                    }
-                }
-            }
-        } else {
+        {
             const int lane = threadIdx.x & 63;
             const int64_t sl = c >> 8;
             const int32_t eb = a.dn_ell4_off[sl];
@@ -957,7 +753,7 @@ __global__ __launch_bounds__(BS) void k_upb(ApplyArgs<TX, TA> a, int64_t band, i
     using V = typename V4<TX>::t;
     const int64_t ddn = a.ddn;
     const int64_t G = (a.dup + rw - 1) / rw;
-    const int64_t bi = blockIdx.x / G;
+    const int64_t bi = blockIdx.x / G;  // band-major
     const int64_t g = blockIdx.x - bi * G;
     const int64_t u0 = g * rw;
     const int nr = (int)((a.dup - u0) < rw ? (a.dup - u0) : rw);
@@ -969,7 +765,7 @@ __global__ __launch_bounds__(BS) void k_upb(ApplyArgs<TX, TA> a, int64_t band, i
         int64_t u[RB];
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
-            u[rr] = u0 + r0 + rr;
+            u[rr] = u0 + (r0 + rr < nr ? r0 + rr : 0);
             const bool ok = r0 + rr < nr;
             if (ok && full) {
                 const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.y + u[rr] * ddn + c));
@@ -1087,48 +883,20 @@ struct Variant {
     int rw;        // kind 7: rows per workgroup of the band pass
 };
 static const Variant kVariants[] = {
+    // row tiles, row-major LDS (generic: no packed-table requirement)
     {0, 1, 256, 0, "rw_r1_b256"},          {0, 2, 256, 0, "rw_r2_b256"},
-    {0, 4, 256, 0, "rw_r4_b256"},          {0, 8, 256, 0, "rw_r8_b256"},
-    {0, 16, 256, 0, "rw_r16_b256"},        {0, 8, 512, 0, "rw_r8_b512"},
-    {1, 8, 256, 512, "tp_r8_band512"},     {1, 8, 256, 2048, "tp_r8_band2048"},
-    {1, 16, 256, 512, "tp_r16_band512"},   {1, 16, 256, 2048, "tp_r16_band2048"},
-    {2, 2, 512, 32, "cs_rr2_rw32"},        {2, 4, 512, 32, "cs_rr4_rw32"},
-    {2, 4, 512, 8, "cs_rr4_rw8"},          {2, 4, 512, 128, "cs_rr4_rw128"},
-    {3, 4, 512, 32, "cstp_rr4_rw32"},      {3, 2, 512, 32, "cstp_rr2_rw32"},
+    // row tiles over the packed 64-state ELL
     {4, 1, 256, 0, "rwpk_r1_b256"},        {4, 2, 512, 0, "rwpk_r2_b512"},
     {4, 4, 512, 0, "rwpk_r4_b512"},        {4, 2, 256, 0, "rwpk_r2_b256"},
-    {5, 8, 256, 512, "tppk_r8_band512"},   {5, 16, 256, 512, "tppk_r16_band512"},
-    {4, 4, 512, 4096, "rwpk_r4_b512_w4k"},  {4, 8, 512, 2048, "rwpk_r8_b512_w2k"},
-    {4, 4, 1024, 0, "rwpk_r4_b1024"},       {4, 2, 512, 4096, "rwpk_r2_b512_w4k"},
-    // transposed row tiles, single pass (kind 6) and row pass + band pass (kind 7)
+    {4, 4, 1024, 0, "rwpk_r4_b1024"},
+    // transposed row tiles, four columns per thread, single pass
     {6, 1, 256, 0, "rt_r1_b256"},           {6, 2, 256, 0, "rt_r2_b256"},
-    {6, 2, 512, 0, "rt_r2_b512"},           {6, 4, 256, 0, "rt_r4_b256"},
-    {6, 4, 512, 0, "rt_r4_b512"},           {6, 1, 512, 0, "rt_r1_b512"},
-    {7, 1, 256, 256, "rt2_r1_b256_band256", 0, 8},
-    {7, 1, 256, 512, "rt2_r1_b256_band512", 0, 8},
-    {7, 1, 256, 256, "rt2_r1_b256_w12k_band256", 12288, 8},
-    {7, 2, 256, 256, "rt2_r2_b256_w6k_band256", 6144, 8},
-    {7, 1, 256, 1024, "rt2_r1_b256_w12k_band1024", 12288, 16},
-    {7, 2, 512, 256, "rt2_r2_b512_band256", 0, 4},
-    // column-stationary row pass + band pass with the four-fermion terms
+    {6, 2, 512, 0, "rt_r2_b512"},           {6, 4, 512, 0, "rt_r4_b512"},
+    {6, 1, 512, 0, "rt_r1_b512"},
+    // column-stationary row pass + band pass with H_up (x) 1 and the four-fermion terms
     {8, 2, 512, 256, "csx_rr2_rw32_band256", 0, 8},
     {8, 2, 512, 512, "csx_rr2_rw32_band512", 0, 8},
     {8, 4, 512, 256, "csx_rr4_rw32_band256", 0, 8},
-    // transposed row tiles over the bond-ordered hop table
-    {9, 1, 256, 0, "rtb_r1_b256"},          {9, 2, 256, 0, "rtb_r2_b256"},
-    {9, 2, 512, 0, "rtb_r2_b512"},          {9, 1, 512, 0, "rtb_r1_b512"},
-    {9, 4, 256, 0, "rtb_r4_b256"},
-    // transposed row tiles aligned to the four-fermion row groups
-    {10, 4, 256, 0, "rtg_r4_b256"},         {10, 4, 512, 0, "rtg_r4_b512"},
-    {10, 4, 256, 0, "rtg_r4_b256_w4k", 4096},
-    {10, 4, 512, 0, "rtg_r4_b512_w4k", 4096},
-    {10, 4, 1024, 0, "rtg_r4_b1024"},       {10, 2, 512, 0, "rtg_r2_b512"},
-    // packed group tiles: a 4-slot tile holds whole four-fermion row groups
-    // (a group of 3 rows with a single row, ...), rows need not be adjacent
-    {11, 4, 512, 0, "rtp_r4_b512"},         {11, 4, 256, 0, "rtp_r4_b256"},
-    {11, 4, 1024, 0, "rtp_r4_b1024"},
-    {11, 4, 512, 0, "rtp_r4_b512_w4k", 4096}, {11, 4, 256, 0, "rtp_r4_b256_w4k", 4096},
-    {11, 2, 512, 0, "rtp_r2_b512"},
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static constexpr int64_t kDynBudget = 163840 - 8192;  // LDS left for the staged x block
@@ -1222,9 +990,6 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.dn_ell_pk = Dn.ell_pk.as<uint32_t>();
     a.dn_ell4_off = Dn.ell4_off.as<int32_t>();
     a.dn_ell4 = Dn.ell4.as<uint4>();
-    a.nbond = Dn.nbond;
-    a.dn_ell4b = Dn.ell4b.as<uint4>();
-    a.dn_bamp = Dn.bamp64.as<double>();
     a.amp_tab = Dn.amp64.as<double>();
     a.namp = Dn.namp;
     a.dn_e = Dn.ediag64.as<double>();
@@ -1245,8 +1010,6 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.xl_amp = h->xl_amp64.as<double>();
     a.partials = partials;
     a.theta = theta;
-    a.tiles = nullptr;
-    a.ntiles = 0;
     return a;
 }
 
@@ -1276,9 +1039,6 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.dn_ell_pk = Dn.ell_pk.as<uint32_t>();
     a.dn_ell4_off = Dn.ell4_off.as<int32_t>();
     a.dn_ell4 = Dn.ell4.as<uint4>();
-    a.nbond = Dn.nbond;
-    a.dn_ell4b = Dn.ell4b.as<uint4>();
-    a.dn_bamp = Dn.bamp32.as<float>();
     a.amp_tab = Dn.amp32.as<float>();
     a.namp = Dn.namp;
     a.dn_e = Dn.ediag32.as<float>();
@@ -1299,8 +1059,6 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.xl_amp = h->xl_amp32.as<float>();
     a.partials = partials;
     a.theta = theta;
-    a.tiles = nullptr;
-    a.ntiles = 0;
     return a;
 }
 
@@ -1345,142 +1103,18 @@ static int64_t launch_rw(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_
     return G * nwin;
 }
 
-template <typename TX, typename TA>
-static void launch_band(const ApplyArgs<TX, TA> &a, int64_t band, hipStream_t s) {
-    constexpr int RB = 8;
-    const int64_t G = (a.dup + RB - 1) / RB;
-    const int64_t nb = (a.ddn + band - 1) / band;
-    k_apply_band<TX, TA, RB, 256><<<(unsigned)(G * nb), 256, 0, s>>>(a, band);
-    ED_LAUNCH_CHECK();
-}
-
-// Row tiles of at most R rows (R <= 4) that never split a group of rows
-// joined by the up-spin moves of the four-fermion terms, so the four-fermion
-// partners of a tile are staged with it.  A tile lists the rank of the row in
-// each slot (-1 = unused).  packed = false: consecutive groups are packed in
-// order; packed = true: groups are packed best-fit regardless of position (a
-// group of 3 rows with a single row, ...).  Groups that are not runs of
-// consecutive ranks, or larger than R, are cut into runs of at most R rows
-// (their partners are then read from memory).
-static const int4 *tiles_for(ed_ham_s *h, int R, bool packed, int *ntiles) {
-    const int key = R + (packed ? 16 : 0);
-    for (size_t i = 0; i < h->tiles.size(); ++i)
-        if (h->tiles[i].first == key) {
-            *ntiles = h->tile_counts[i];
-            return h->tiles[i].second ? h->tiles[i].second->as<int4>() : nullptr;
-        }
-    const int64_t dup = h->dup;
-    std::vector<int4> t;
-    if (h->nx > 0 && dup <= (int64_t)1 << 24) {
-        std::vector<int> qs;
-        for (auto &x : h->xterms)
-            if (std::find(qs.begin(), qs.end(), x.up_mv) == qs.end()) qs.push_back(x.up_mv);
-        std::vector<int32_t> par((size_t)dup);
-        for (int64_t u = 0; u < dup; ++u) par[u] = (int32_t)u;
-        auto find = [&](int32_t u) {
-            while (par[u] != u) u = par[u] = par[par[u]];
-            return u;
-        };
-        std::vector<int32_t> mv((size_t)dup);
-        for (int q : qs) {
-            ED_HIP(hipMemcpy(mv.data(), h->sp[0].mv.as<int32_t>() + (size_t)q * dup, (size_t)dup * sizeof(int32_t),
-                             hipMemcpyDeviceToHost));
-            for (int64_t u = 0; u < dup; ++u)
-                if (mv[u] >= 0) {
-                    const int32_t a = find((int32_t)u), b = find(mv[u] >> 1);
-                    if (a != b) par[std::max(a, b)] = std::min(a, b);
-                }
-        }
-        std::vector<int32_t> lo((size_t)dup, INT32_MAX), hi((size_t)dup, -1), cnt((size_t)dup, 0);
-        for (int64_t u = 0; u < dup; ++u) {
-            const int32_t r = find((int32_t)u);
-            lo[r] = std::min(lo[r], (int32_t)u);
-            hi[r] = std::max(hi[r], (int32_t)u);
-            ++cnt[r];
-        }
-        // runs of consecutive ranks, each at most R rows, in rank order
-        std::vector<std::pair<int32_t, int32_t>> runs;  // (first, length)
-        for (int64_t u = 0; u < dup;) {
-            const int32_t r = find((int32_t)u);
-            if (lo[r] == u && hi[r] - lo[r] + 1 == cnt[r] && cnt[r] <= R) {
-                runs.push_back({(int32_t)u, cnt[r]});
-                u += cnt[r];
-            } else {
-                runs.push_back({(int32_t)u, 1});
-                u += 1;
-            }
-        }
-        auto add = [&](std::vector<int32_t> &slots) {
-            int4 q = make_int4(-1, -1, -1, -1);
-            int32_t *qv = &q.x;
-            for (size_t i = 0; i < slots.size(); ++i) qv[i] = slots[i];
-            t.push_back(q);
-        };
-        if (!packed) {
-            std::vector<int32_t> cur;
-            for (auto &rn : runs) {
-                if ((int)cur.size() + rn.second > R) {
-                    add(cur);
-                    cur.clear();
-                }
-                for (int k = 0; k < rn.second; ++k) cur.push_back(rn.first + k);
-            }
-            if (!cur.empty()) add(cur);
-        } else {
-            // best fit, largest runs first; open tiles kept per free capacity
-            std::vector<std::vector<int32_t>> tl;
-            std::vector<std::vector<int>> open((size_t)R + 1);
-            std::vector<size_t> order(runs.size());
-            for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-            std::stable_sort(order.begin(), order.end(),
-                             [&](size_t x, size_t y) { return runs[x].second > runs[y].second; });
-            for (size_t oi : order) {
-                const int len = runs[oi].second;
-                int ti = -1;
-                for (int cap = len; cap < R && ti < 0; ++cap)
-                    if (!open[cap].empty()) {
-                        ti = open[cap].back();
-                        open[cap].pop_back();
-                    }
-                if (ti < 0) {
-                    ti = (int)tl.size();
-                    tl.emplace_back();
-                }
-                for (int k = 0; k < len; ++k) tl[ti].push_back(runs[oi].first + k);
-                const int fr = R - (int)tl[ti].size();
-                if (fr > 0) open[fr].push_back(ti);
-            }
-            for (auto &v : tl) add(v);
-        }
-    }
-    DevMem *m = nullptr;
-    if (!t.empty()) {
-        m = new DevMem();
-        m->alloc(t.size() * sizeof(int4));
-        ED_HIP(hipMemcpy(m->p, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
-    }
-    h->tiles.push_back({key, m});
-    h->tile_counts.push_back((int)t.size());
-    *ntiles = (int)t.size();
-    return m ? m->as<int4>() : nullptr;
-}
-
-template <typename TX, typename TA, int R, int BS, bool UPX, bool BOND = false>
-static void launch_rt(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t wcap, bool grouped = false,
-                      bool packed = false) {
+template <typename TX, typename TA, int R, int BS>
+static void launch_rt(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t wcap) {
     int nwin = 0, wmax = 0;
-    const int64_t amp_bytes = BOND ? 16 : (int64_t)h->sp[1].namp * (int64_t)sizeof(TA) + 16;
+    const int64_t amp_bytes = (int64_t)h->sp[1].namp * (int64_t)sizeof(TA) + 16;
     int64_t cap = (kDynBudget - amp_bytes) / (int64_t)(R * sizeof(TX));
     if (wcap > 0 && wcap < cap) cap = wcap;
     a.win = windows_for(h, cap, &nwin, &wmax);
     a.nwin = nwin;
     a.wmax = wmax;
-    int ntiles = 0;
-    a.tiles = grouped ? tiles_for(h, R, packed, &ntiles) : nullptr;
-    a.ntiles = ntiles;
-    const int64_t G = a.tiles ? (int64_t)ntiles : (a.dup + R - 1) / R;
+    const int64_t G = (a.dup + R - 1) / R;
     const size_t shm = (((size_t)R * (size_t)wmax * sizeof(TX) + 15) & ~(size_t)15) + (size_t)amp_bytes;
-    auto kern = k_rt<TX, TA, R, BS, UPX, true, BOND>;
+    auto kern = k_rt<TX, TA, R, BS, true, true>;
     allow_lds(kern);
     kern<<<(unsigned)(G * nwin), BS, shm, s>>>(a);
     ED_LAUNCH_CHECK();
@@ -1544,113 +1178,36 @@ static int64_t launch_cs(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStr
     fail(ED_EINVAL, "column-stationary schedule does not fit this Hamiltonian");
 }
 
-template <typename TX, typename TA, int RR, int UMAX>
-static void launch_csb_u(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
-    constexpr int BS = 512;
-    const int64_t band = BS;
-    const int64_t G = (a.dup + rw - 1) / rw;
-    const int64_t nb = (a.ddn + band - 1) / band;
-    const int nm = cs_nmv(h), xm = cs_xmax(h);
-    if (nm == 0)
-        k_csb<TX, TA, BS, RR, UMAX, 0, 0><<<(unsigned)(G * nb), BS, 0, s>>>(a, band, rw);
-    else if (xm == 4)
-        k_csb<TX, TA, BS, RR, UMAX, 8, 4><<<(unsigned)(G * nb), BS, 0, s>>>(a, band, rw);
-    else
-        k_csb<TX, TA, BS, RR, UMAX, 8, 8><<<(unsigned)(G * nb), BS, 0, s>>>(a, band, rw);
-    ED_LAUNCH_CHECK();
-}
-
-template <typename TX, typename TA, int RR>
-static void launch_csb(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
-    const int km = cs_kmax(h);
-    if (km == 8) launch_csb_u<TX, TA, RR, 8>(h, a, rw, s);
-    else if (km == 16) launch_csb_u<TX, TA, RR, 16>(h, a, rw, s);
-    else launch_csb_u<TX, TA, RR, 32>(h, a, rw, s);
-}
-
 template <typename TX, typename TA>
 static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipStream_t s) {
     const Variant &V = kVariants[v];
     switch (v) {
         case 0: launch_rw<TX, TA, 1, 256, 0, true>(h, a, s); break;
         case 1: launch_rw<TX, TA, 2, 256, 0, true>(h, a, s); break;
-        case 2: launch_rw<TX, TA, 4, 256, 0, true>(h, a, s); break;
-        case 3: launch_rw<TX, TA, 8, 256, 0, true>(h, a, s); break;
-        case 4: launch_rw<TX, TA, 16, 256, 0, true>(h, a, s); break;
-        case 5: launch_rw<TX, TA, 8, 512, 0, true>(h, a, s); break;
-        case 6:
-        case 7: launch_rw<TX, TA, 8, 256, 0, false>(h, a, s); launch_band(a, V.band, s); break;
-        case 8:
-        case 9: launch_rw<TX, TA, 16, 256, 0, false>(h, a, s); launch_band(a, V.band, s); break;
-        case 10: launch_cs<TX, TA, 2, 0, true>(h, a, (int)V.band, s); break;
-        case 11:
+        case 2: launch_rw<TX, TA, 1, 256, 0, true, true>(h, a, s); break;
+        case 3: launch_rw<TX, TA, 2, 512, 0, true, true>(h, a, s); break;
+        case 4: launch_rw<TX, TA, 4, 512, 0, true, true>(h, a, s); break;
+        case 5: launch_rw<TX, TA, 2, 256, 0, true, true>(h, a, s); break;
+        case 6: launch_rw<TX, TA, 4, 1024, 0, true, true>(h, a, s); break;
+        case 7: launch_rt<TX, TA, 1, 256>(h, a, s, V.wcap); break;
+        case 8: launch_rt<TX, TA, 2, 256>(h, a, s, V.wcap); break;
+        case 9: launch_rt<TX, TA, 2, 512>(h, a, s, V.wcap); break;
+        case 10: launch_rt<TX, TA, 4, 512>(h, a, s, V.wcap); break;
+        case 11: launch_rt<TX, TA, 1, 512>(h, a, s, V.wcap); break;
         case 12:
-        case 13: launch_cs<TX, TA, 4, 0, true>(h, a, (int)V.band, s); break;
-        case 14: launch_cs<TX, TA, 4, 0, false>(h, a, (int)V.band, s); launch_csb<TX, TA, 4>(h, a, 32, s); break;
-        case 15: launch_cs<TX, TA, 2, 0, false>(h, a, (int)V.band, s); launch_csb<TX, TA, 2>(h, a, 32, s); break;
-        case 16: launch_rw<TX, TA, 1, 256, 0, true, true>(h, a, s); break;
-        case 17: launch_rw<TX, TA, 2, 512, 0, true, true>(h, a, s); break;
-        case 18: launch_rw<TX, TA, 4, 512, 0, true, true>(h, a, s); break;
-        case 19: launch_rw<TX, TA, 2, 256, 0, true, true>(h, a, s); break;
-        case 20: launch_rw<TX, TA, 8, 256, 0, false, true>(h, a, s); launch_band(a, V.band, s); break;
-        case 21: launch_rw<TX, TA, 16, 256, 0, false, true>(h, a, s); launch_band(a, V.band, s); break;
-        case 22: launch_rw<TX, TA, 4, 512, 0, true, true>(h, a, s, V.band); break;
-        case 23: launch_rw<TX, TA, 8, 512, 0, true, true>(h, a, s, V.band); break;
-        case 24: launch_rw<TX, TA, 4, 1024, 0, true, true>(h, a, s); break;
-        case 25: launch_rw<TX, TA, 2, 512, 0, true, true>(h, a, s, V.band); break;
-        case 26: launch_rt<TX, TA, 1, 256, true>(h, a, s, V.wcap); break;
-        case 27: launch_rt<TX, TA, 2, 256, true>(h, a, s, V.wcap); break;
-        case 28: launch_rt<TX, TA, 2, 512, true>(h, a, s, V.wcap); break;
-        case 29: launch_rt<TX, TA, 4, 256, true>(h, a, s, V.wcap); break;
-        case 30: launch_rt<TX, TA, 4, 512, true>(h, a, s, V.wcap); break;
-        case 31: launch_rt<TX, TA, 1, 512, true>(h, a, s, V.wcap); break;
-        case 32:
-        case 33:
-        case 34:
-        case 36: launch_rt<TX, TA, 1, 256, false>(h, a, s, V.wcap); launch_upb(a, V.band, V.rw, s); break;
-        case 35: launch_rt<TX, TA, 2, 256, false>(h, a, s, V.wcap); launch_upb(a, V.band, V.rw, s); break;
-        case 37: launch_rt<TX, TA, 2, 512, false>(h, a, s, V.wcap); launch_upb(a, V.band, V.rw, s); break;
-        case 38:
-        case 39: launch_cs<TX, TA, 2, 0, false>(h, a, 32, s); launch_upb<TX, TA, true>(a, V.band, V.rw, s); break;
-        case 40: launch_cs<TX, TA, 4, 0, false>(h, a, 32, s); launch_upb<TX, TA, true>(a, V.band, V.rw, s); break;
-        case 41: launch_rt<TX, TA, 1, 256, true, true>(h, a, s, V.wcap); break;
-        case 42: launch_rt<TX, TA, 2, 256, true, true>(h, a, s, V.wcap); break;
-        case 43: launch_rt<TX, TA, 2, 512, true, true>(h, a, s, V.wcap); break;
-        case 44: launch_rt<TX, TA, 1, 512, true, true>(h, a, s, V.wcap); break;
-        case 45: launch_rt<TX, TA, 4, 256, true, true>(h, a, s, V.wcap); break;
-        case 46:
-        case 48: launch_rt<TX, TA, 4, 256, true>(h, a, s, V.wcap, true); break;
-        case 47:
-        case 49: launch_rt<TX, TA, 4, 512, true>(h, a, s, V.wcap, true); break;
-        case 50: launch_rt<TX, TA, 4, 1024, true>(h, a, s, V.wcap, true); break;
-        case 51: launch_rt<TX, TA, 2, 512, true>(h, a, s, V.wcap, true); break;
-        case 52:
-        case 55: launch_rt<TX, TA, 4, 512, true>(h, a, s, V.wcap, true, true); break;
-        case 53:
-        case 56: launch_rt<TX, TA, 4, 256, true>(h, a, s, V.wcap, true, true); break;
-        case 54: launch_rt<TX, TA, 4, 1024, true>(h, a, s, V.wcap, true, true); break;
-        case 57: launch_rt<TX, TA, 2, 512, true>(h, a, s, V.wcap, true, true); break;
+        case 13: launch_cs<TX, TA, 2, 0, false>(h, a, 32, s); launch_upb<TX, TA, true>(a, V.band, V.rw, s); break;
+        case 14: launch_cs<TX, TA, 4, 0, false>(h, a, 32, s); launch_upb<TX, TA, true>(a, V.band, V.rw, s); break;
         default: fail(ED_EINVAL, "bad apply variant %d", v);
     }
 }
 
 static bool variant_fits(const ed_ham_s *h, int v, size_t elem) {
+    (void)elem;
     if (v < 0 || v >= kNumVariants) return false;
     const Variant &V = kVariants[v];
-    if ((V.kind == 1 || V.kind == 3) && h->nx == 0 && h->sp[0].nnz == 0) return false;  // no second pass
-    if ((V.kind == 2 || V.kind == 3) && (cs_kmax(h) == 0 || cs_nmv(h) < 0 || (h->nx > 0 && cs_xmax(h) == 0)))
+    if (V.kind == 4 && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->sp[1].nmv > 8))
         return false;
-    if ((V.kind == 4 || V.kind == 5) && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->sp[1].nmv > 8))
-        return false;
-    if (V.kind == 5 && h->nx == 0 && h->sp[0].nnz == 0) return false;
-    if ((V.kind == 6 || V.kind == 7 || V.kind == 9 || V.kind == 10 || V.kind == 11) && h->koff > 4) return false;
-    if ((V.kind == 6 || V.kind == 7) && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16))
-        return false;
-    if (V.kind == 7 && h->sp[0].nnz == 0) return false;
-    if ((V.kind == 10 || V.kind == 11) && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->nx == 0))
-        return false;
-    if (V.kind == 9 && (h->sp[1].nbond == 0 || !h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16))
-        return false;
+    if (V.kind == 6 && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->koff > 4)) return false;
     if (V.kind == 8 && (h->sp[0].nnz == 0 || cs_kmax(h) == 0 || cs_nmv(h) < 0 || (h->nx > 0 && cs_xmax(h) == 0)))
         return false;
     return true;

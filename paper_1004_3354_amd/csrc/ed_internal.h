@@ -139,10 +139,6 @@ struct SpinTab {
     // slices): ell4_off [nslices4+1] in uint4 units, ell4 uint4 [(slice, k, lane)]
     int64_t nslices4 = 0;
     DevMem ell4_off, ell4;
-    // bond-ordered four-state ELL (nbond > 0 when built): uint4 [(slice, bond, lane)],
-    // entry = target | negative sign << 20 | active << 21; bond amplitudes bamp
-    int nbond = 0;
-    DevMem ell4b, bamp64, bamp32;
     DevMem ediag64, ediag32;  // one-spin diagonal piece: eps n + same-spin density terms
     DevMem cidx;              // uint8 [dim] bits of the state on the cross-term support
     int nmv = 0;              // number of move tables
@@ -197,13 +193,8 @@ struct ed_ham_s {
     std::vector<uint32_t> dn_states_host;           // for the LDS window plan
     std::vector<std::pair<int64_t, ed::DevMem *>> windows;  // (capacity, device int2 list)
     std::vector<int> window_counts;
-    // row tiles of at most R rows that keep each group of rows joined by the
-    // four-fermion up-spin moves together: (R + 16 * packed, device int4 slot list)
-    std::vector<std::pair<int, ed::DevMem *>> tiles;
-    std::vector<int> tile_counts;
     ~ed_ham_s() {
         for (auto &w : windows) delete w.second;
-        for (auto &t : tiles) delete t.second;
     }
 };
 
@@ -230,9 +221,6 @@ struct ApplyArgs {
     const uint32_t *dn_ell_pk;
     const int32_t *dn_ell4_off;
     const uint4 *dn_ell4;
-    int nbond;
-    const uint4 *dn_ell4b;
-    const TA *dn_bamp;
     const TA *amp_tab;
     int namp;
     const uint32_t *dn_st;
@@ -257,10 +245,6 @@ struct ApplyArgs {
     const int2 *win;
     int nwin;
     int wmax;
-    // row tiles: rank of the row in each slot (-1 = unused); nullptr =
-    // consecutive tiles of R rows
-    const int4 *tiles;
-    int ntiles;
 };
 
 // Build all tables of a Hamiltonian handle (tables.hip).

@@ -391,56 +391,6 @@ static void build_spin(ed_ham_s *h, int s, const BasisData &b, const ed_params *
             t.nslices4 = n4;
             upload(t.ell4_off, o4);
             upload(t.ell4, e4);
-            // bond-ordered form: slot b of every state is bond b = {i < j}, so the
-            // amplitude is the bond's (uniform across a wave) times the fermion
-            // sign, and within a slot the targets of consecutive states increase
-            // piecewise.  Entry: target (bits 0..19) | negative sign (bit 20) |
-            // active (bit 21); inactive slots point at the state itself.
-            std::map<std::pair<int, int>, int> bidx;
-            std::vector<double> bamp;
-            bool bok = true;
-            for (size_t q = 0; q < pairs.size(); ++q) {
-                const int i = std::min(pairs[q].x, pairs[q].y), j = std::max(pairs[q].x, pairs[q].y);
-                auto it = bidx.find({i, j});
-                if (it == bidx.end()) {
-                    bidx[{i, j}] = (int)bamp.size();
-                    bamp.push_back(pamp[q]);
-                } else if (bamp[it->second] != pamp[q]) {
-                    bok = false;  // h_ij != h_ji: no single amplitude per bond
-                }
-            }
-            const int nb = (int)bamp.size();
-            t.nbond = 0;
-            if (bok && nb > 0 && nb <= 32) {
-                std::vector<uint32_t> hst((size_t)dim);
-                ED_HIP(hipMemcpy(hst.data(), t.states.p, (size_t)dim * sizeof(uint32_t), hipMemcpyDeviceToHost));
-                std::vector<uint32_t> eb((size_t)n4 * nb * 256);
-                for (int64_t sl = 0; sl < n4 && bok; ++sl)
-                    for (int l = 0; l < 256 && bok; ++l) {
-                        const int64_t q = sl * 256 + l;
-                        const uint32_t self = (uint32_t)std::min<int64_t>(q, dim - 1);
-                        for (int k = 0; k < nb; ++k) eb[((size_t)sl * nb + k) * 256 + l] = self;
-                        if (q >= dim) continue;
-                        for (int32_t e = ho[q]; e < ho[q + 1]; ++e) {
-                            const uint32_t df = hst[q] ^ hst[ht[e]];
-                            const int i = __builtin_ctz(df), j = 31 - __builtin_clz(df);
-                            auto it = bidx.find({i, j});
-                            if (__builtin_popcount(df) != 2 || it == bidx.end()) { bok = false; break; }
-                            const double am = bamp[it->second];
-                            uint32_t v = (uint32_t)ht[e] | (1u << 21);
-                            if (hs[e] == -am && hs[e] != am) v |= 1u << 20;
-                            else if (hs[e] != am) { bok = false; break; }
-                            eb[((size_t)sl * nb + it->second) * 256 + l] = v;
-                        }
-                    }
-                if (bok) {
-                    t.nbond = nb;
-                    upload(t.ell4b, eb);
-                    upload(t.bamp64, bamp);
-                    std::vector<float> b32(bamp.begin(), bamp.end());
-                    upload(t.bamp32, b32);
-                }
-            }
         }
     }
 
