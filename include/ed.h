@@ -183,7 +183,11 @@ typedef struct {
     int32_t max_iter;     /* total Lanczos steps over all restarts (default 600)    */
     int32_t max_basis;    /* stored basis vectors before a restart (default 120)    */
     double tol;           /* stop when |beta_j s_j| <= tol * max(|theta|, 1) (1e-10) */
-    int32_t reorth;       /* Gram-Schmidt passes per step: 0, 1 or 2 (default 2)    */
+    int32_t reorth;       /* Gram-Schmidt per step (default 2): 0 = three-term only, 1 = one
+                             full pass, 2 = two full passes (CGS2), 3 = the two projections
+                             of CGS2 from one read of the basis, the second one's
+                             coefficients through the Gram matrix of the stored vectors
+                             (ground state; with locked vectors it falls back to 2)    */
     int32_t check_every;  /* steps between convergence tests (default 4)            */
     int32_t refine;       /* 1: report the FP64 Rayleigh quotient of the Ritz vector */
 } ed_lanczos_opts;

@@ -10,6 +10,11 @@
 //   a_i = <S_i, Y> over locked vectors and S_0..S_j, gamma_i = sigma_i^2 a_i
 //   Y <- Y - sum_i gamma_i S_i                 (classical Gram-Schmidt)
 //   repeated once more ("twice is enough"), alpha_j = sum of the two gamma_j
+// reorth = 3 gives the same two projections with one read of the basis per
+// step: the second pass's dots are a_i - sum_k G_ik gamma_k with G_ik =
+// <S_i, S_k> (exact for the update Y - sum gamma_k S_k), and the new row of G
+// comes from the same multi-dot, which reads the basis once for two
+// right-hand sides (Y and S_j); one update with the summed coefficients follows.
 //   beta_j = sigma_j ||Y||, sigma_{j+1} = 1 / ||Y||, S_{j+1} = Y
 // All dot products and updates accumulate in FP64 with a fixed reduction
 // order, so runs are bit-reproducible.  The lowest eigenpair of the j x j
@@ -87,6 +92,45 @@ __global__ __launch_bounds__(kRedBS) void k_multidot(const TX *const *vecs, int 
     }
 }
 
+// Two right-hand sides in one read of the basis:
+// partials[v * nblk + blk] = sum S_v Y, partials[(nvec + v) * nblk + blk] = sum S_v Z
+template <typename TX, int G>
+__global__ __launch_bounds__(kRedBS) void k_multidot2(const TX *const *vecs, int nvec, const TX *y, const TX *z,
+                                                      int64_t n, double *partials) {
+    __shared__ double red[kRedBS / 64];
+    const int nblk = gridDim.x, blk = blockIdx.x;
+    int64_t a, b;
+    block_range(n, nblk, blk, a, b);
+    for (int g0 = 0; g0 < nvec; g0 += G) {
+        double ay[G], az[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) ay[i] = az[i] = 0.0;
+        const TX *vp[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) vp[i] = vecs[(g0 + i < nvec) ? g0 + i : g0];
+        for (int64_t k = a + threadIdx.x; k < b; k += kRedBS) {
+            const double yv = (double)y[k], zv = (double)z[k];
+#pragma unroll
+            for (int i = 0; i < G; ++i)
+                if (g0 + i < nvec) {
+                    const double sv = (double)vp[i][k];
+                    ay[i] += sv * yv;
+                    az[i] += sv * zv;
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (g0 + i >= nvec) break;
+            const double sy = block_sum_any<kRedBS>(ay[i], red);
+            const double sz = block_sum_any<kRedBS>(az[i], red);
+            if (threadIdx.x == 0) {
+                partials[(int64_t)(g0 + i) * nblk + blk] = sy;
+                partials[(int64_t)(nvec + g0 + i) * nblk + blk] = sz;
+            }
+        }
+    }
+}
+
 // Y[n] = post * ((assign ? 0 : Y[n]) - sum_i coef[i] S_i[n]) with post =
 // sqrt(*post_sig2) (1 if NULL); optional norm partials of the stored result.
 template <typename TX>
@@ -151,6 +195,47 @@ __global__ void k_finalize_dots(const double *partials, int nvec, int nblk, cons
         __syncthreads();
     }
     if (threadIdx.x == 0 && alpha && gamma) *alpha += gamma[jidx];
+}
+
+// Coefficients of both projections from one two-sided multi-dot (reorth = 3).
+// a_i = <S_i, Y>, g_i = <S_i, S_jr> (jr = nvec - 1, the newest vector): row jr
+// of the Gram matrix G (ld x ld) is set from g, then gamma1_i = sig2_i a_i,
+// a2_i = a_i - sum_k G_ik gamma1_k, gamma_i = gamma1_i + sig2_i a2_i, and
+// *alpha += gamma_jr.  Fixed-order sums; one workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_finalize_gram(const double *partials, int nvec, int nblk,
+                                                       const double *sig2, double *gram, int ld, double *gamma,
+                                                       double *alpha) {
+    __shared__ double sh[256];
+    __shared__ double av[kMaxVec], g1[kMaxVec];
+    const int jr = nvec - 1;
+    for (int v = 0; v < 2 * nvec; ++v) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nblk; i += 256) s += partials[(int64_t)v * nblk + i];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (v < nvec) {
+                av[v] = sh[0];
+                g1[v] = sig2[v] * sh[0];
+            } else {
+                const int i = v - nvec;
+                gram[(int64_t)jr * ld + i] = sh[0];
+                gram[(int64_t)i * ld + jr] = sh[0];
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nvec; i += 256) {
+        double t = 0.0;
+        for (int k = 0; k < nvec; ++k) t += gram[(int64_t)i * ld + k] * g1[k];
+        gamma[i] = g1[i] + sig2[i] * (av[i] - t);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && alpha) *alpha += gamma[jr];
 }
 
 // After the last update of step j the stored Y is w'' = sigma_j (Y - ...):
@@ -352,6 +437,7 @@ struct Work {
     const void **vp = nullptr;   // device array of vector pointers [kmax + m + 1]
     double *sig2 = nullptr, *gamma = nullptr, *raw = nullptr, *alpha = nullptr, *beta = nullptr;
     double *partials = nullptr, *tri = nullptr, *triwork = nullptr, *coef = nullptr;
+    double *gram = nullptr;      // (m+1) x (m+1) Gram matrix of the stored vectors (reorth = 3)
 };
 
 static void fill_defaults(ed_lanczos_opts &o) {
@@ -372,7 +458,7 @@ static ed_lanczos_opts effective(const ed_lanczos_opts *opts, int64_t D) {
     if (o.max_basis > 1000) o.max_basis = 1000;
     if ((int64_t)o.max_basis > D) o.max_basis = (int)std::max<int64_t>(D, 1);
     if (!(o.tol > 0.0)) o.tol = 1e-10;
-    if (o.reorth < 0 || o.reorth > 2) o.reorth = 2;
+    if (o.reorth < 0 || o.reorth > 3) o.reorth = 2;
     if (o.check_every <= 0) o.check_every = 4;
     return o;
 }
@@ -397,7 +483,8 @@ static size_t layout(Work &w, char *base, int64_t D, size_t elem, int m, int kma
     w.coef = (double *)c.take((size_t)nv * sizeof(double));
     w.alpha = (double *)c.take((size_t)(m + 2) * sizeof(double));
     w.beta = (double *)c.take((size_t)(m + 2) * sizeof(double));
-    w.partials = (double *)c.take((size_t)nv * (size_t)w.nblk * sizeof(double));
+    w.partials = (double *)c.take((size_t)2 * nv * (size_t)w.nblk * sizeof(double));
+    w.gram = (double *)c.take((size_t)(m + 1) * (size_t)(m + 1) * sizeof(double));
     w.tri = (double *)c.take((size_t)(m + 8) * sizeof(double));
     w.triwork = (double *)c.take((size_t)(8 + 6 * (m + 2)) * sizeof(double) + (size_t)(m + 2) * sizeof(int) + 64);
     return c.off + 256;
@@ -429,6 +516,18 @@ struct Solver {
         if (h->prec == ED_FP64) multidot<double>(vbeg, nvec, y);
         else multidot<float>(vbeg, nvec, y);
         k_finalize_dots<<<1, 256, 0, s>>>(w.partials, nvec, w.nblk, w.sig2 + vbeg, w.raw, w.gamma + vbeg, alpha, jrel);
+        ED_LAUNCH_CHECK();
+    }
+    // both projections of one step from a single read of the basis (reorth = 3)
+    void dots_gram(int nvec, const void *y, const void *z, double *alpha) {
+        if (h->prec == ED_FP64)
+            k_multidot2<double, 16><<<w.nblk, kRedBS, 0, s>>>((const double *const *)w.vp, nvec, (const double *)y,
+                                                             (const double *)z, h->D, w.partials);
+        else
+            k_multidot2<float, 16><<<w.nblk, kRedBS, 0, s>>>((const float *const *)w.vp, nvec, (const float *)y,
+                                                            (const float *)z, h->D, w.partials);
+        ED_LAUNCH_CHECK();
+        k_finalize_gram<<<1, 256, 0, s>>>(w.partials, nvec, w.nblk, w.sig2, w.gram, w.m + 1, w.gamma, alpha);
         ED_LAUNCH_CHECK();
     }
     void update(int vbeg, int nvec, void *y, double *normp, const double *post = nullptr) {
@@ -514,12 +613,20 @@ struct Solver {
                     vb = nlock + j - 1;
                     nvec = 2;
                 }
-                const int passes = o.reorth == 2 ? 2 : 1;
-                for (int ps = 0; ps < passes; ++ps) {
-                    const bool last_pass = ps == passes - 1;
-                    dots(vb, nvec, Y, w.alpha + j, nlock + j - vb);
-                    // the last pass also scales by sigma_j: the stored vector is w''
-                    update(vb, nvec, Y, last_pass ? w.partials : nullptr, last_pass ? w.sig2 + nlock + j : nullptr);
+                if (o.reorth == 3 && nlock == 0) {
+                    // one two-sided multi-dot (Y and S_j) and one update with the
+                    // coefficients of both projections; scaled by sigma_j like below
+                    dots_gram(nv, Y, kr[j], w.alpha + j);
+                    update(0, nv, Y, w.partials, w.sig2 + j);
+                } else {
+                    const int passes = o.reorth >= 2 ? 2 : 1;
+                    for (int ps = 0; ps < passes; ++ps) {
+                        const bool last_pass = ps == passes - 1;
+                        dots(vb, nvec, Y, w.alpha + j, nlock + j - vb);
+                        // the last pass also scales by sigma_j: the stored vector is w''
+                        update(vb, nvec, Y, last_pass ? w.partials : nullptr,
+                               last_pass ? w.sig2 + nlock + j : nullptr);
+                    }
                 }
                 k_finalize_norm<<<1, 256, 0, s>>>(w.partials, w.nblk, w.sig2, w.beta, nlock + j, j);
                 ED_LAUNCH_CHECK();

@@ -77,6 +77,47 @@ def test_ground_state_small(name, phys, nn, prec):
     assert r <= max(10 * info["residual"], 1e-9)
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("max_basis", [120, 12], ids=["basis120", "basis12_restarts"])
+@pytest.mark.parametrize("name,phys,nn", [
+    ("kan9_45", wl.kanamori(3, 2, 2.3, 0.4, seed=3), (4, 5)),
+    ("hub3x3_45", wl.hubbard(3, 3, 1.0, 4.0), (4, 5)),
+], ids=["kan9_45", "hub3x3_45"])
+def test_ground_state_single_read_projections(name, phys, nn, max_basis, prec):
+    """reorth = 3: both Gram-Schmidt projections from one read of the basis
+    (second-pass coefficients through the Gram matrix) reach the oracle E0 to
+    the same tolerance as two full passes, also across restarts."""
+    ed = gpu_ed()
+    b, H = build(phys, *nn, prec)
+    sec = sector(phys, *nn)
+    e_ref = orc.lowest_k(sec, 1, tol=1e-14)[0]
+    psi = torch.empty(b.D, dtype=torch.float64 if prec == 0 else torch.float32, device=DEV)
+    E, info = H.lanczos_ground(_v0(b.D, prec), ed.options(tol=1e-10 if prec == 0 else 1e-7, reorth=3,
+                                                           max_basis=max_basis, max_iter=3000), psi=psi)
+    assert info["converged"] == 1
+    assert _rel(E, e_ref) <= TOL[prec], (E, e_ref)
+    if max_basis == 12:
+        assert info["restarts"] > 0
+    p = psi.double().cpu().numpy()
+    r = np.linalg.norm(sec.spmv(p) - E * p)
+    assert r <= max(10 * info["residual"], 1e-9)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_single_read_projections_match_cgs2(prec):
+    """Same start vector, same Krylov space: the two orthogonalisation forms
+    give the same E0 and about the same number of steps."""
+    ed = gpu_ed()
+    phys, _ = wl.config(3)
+    b, H = build(phys, 6, 6, prec)
+    v0 = _v0(b.D, prec)
+    tol = 1e-10 if prec == 0 else 1e-7
+    E2, i2 = H.lanczos_ground(v0, ed.options(tol=tol, reorth=2, max_basis=80))
+    E3, i3 = H.lanczos_ground(v0, ed.options(tol=tol, reorth=3, max_basis=80))
+    assert _rel(E3, E2) <= (1e-11 if prec == 0 else 1e-7), (E2, E3)
+    assert abs(i3["iters"] - i2["iters"]) <= max(8, i2["iters"] // 10), (i2, i3)
+
+
 def test_generic_model_ground_state():
     ed = gpu_ed()
     p = generic_model(9, 4)
@@ -152,15 +193,16 @@ def test_config3_sectors_vs_golden(nn, prec):
     assert _rel(E, e_ref) <= TOL[prec], (E, e_ref, info)
 
 
+@pytest.mark.parametrize("reorth", [2, 3], ids=["cgs2", "single_read"])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("jp", [True, False], ids=["jp_on", "jp_off"])
-def test_config2_full_size_vs_golden(jp, prec):
+def test_config2_full_size_vs_golden(jp, prec, reorth):
     ed = gpu_ed()
     phys, sectors = wl.config(2, jprime=jp)
     e_ref = _golden("cfg2" if jp else "cfg2_jp_off", "7,7")[0]
     b, H = build(phys, 7, 7, prec)
     E, info = H.lanczos_ground(_v0(b.D, prec, wl.start_vector_seed(2)),
-                               ed.options(tol=1e-10 if prec == 0 else 1e-7, max_basis=100))
+                               ed.options(tol=1e-10 if prec == 0 else 1e-7, max_basis=100, reorth=reorth))
     assert _rel(E, e_ref) <= TOL[prec], (E, e_ref, info)
 
 
