@@ -190,6 +190,11 @@ typedef struct {
                              (ground state; with locked vectors it falls back to 2)    */
     int32_t check_every;  /* steps between convergence tests (default 4)            */
     int32_t refine;       /* 1: report the FP64 Rayleigh quotient of the Ritz vector */
+    int32_t keep;         /* restart: 0 = from the current Ritz vector alone (default);
+                             k >= 1 = implicit restart keeping k vectors (the unwanted
+                             Ritz values applied as exact shifts to the tridiagonal
+                             matrix, which stays tridiagonal); ground state only,
+                             k <= 16, k < max_basis <= 256                           */
 } ed_lanczos_opts;
 
 typedef struct {

@@ -30,6 +30,8 @@ namespace ed {
 
 static constexpr int kRedBS = 256;
 static constexpr int kMaxVec = 1024;  // locked + stored basis vectors per kernel
+static constexpr int kIRMaxIn = 257;  // implicit restart: at most 256 basis vectors + the residual
+static constexpr int kIRMaxOut = 17;  // and at most 16 kept vectors + the new residual
 
 int reduce_blocks(int64_t n) {
     int64_t b = (n + 4095) / 4096;
@@ -160,6 +162,44 @@ __global__ __launch_bounds__(kRedBS) void k_lincomb(const TX *const *vecs, const
         const double s = block_sum_any<kRedBS>(nrm, red);
         if (threadIdx.x == 0) norm_part[blockIdx.x] = s;
     }
+}
+
+// Implicit restart, in place: out_o[n] = sum_i C[i * nout + o] in_i[n] for
+// o < nout, where out_o is the storage of in_o (each element's inputs are read
+// by the thread that writes its outputs, before it writes them).  Norm partials
+// of the last output (the new residual).
+template <typename TX>
+__global__ __launch_bounds__(kRedBS) void k_restart_combine(const TX *const *vin, const double *C, int nin, int nout,
+                                                            int64_t n, double *norm_part) {
+    __shared__ double c[kIRMaxIn * kIRMaxOut];
+    __shared__ const TX *pin[kIRMaxIn];
+    __shared__ double red[kRedBS / 64];
+    for (int i = threadIdx.x; i < nin * nout; i += kRedBS) c[i] = C[i];
+    for (int i = threadIdx.x; i < nin; i += kRedBS) pin[i] = vin[i];
+    __syncthreads();
+    int64_t a, b;
+    block_range(n, gridDim.x, blockIdx.x, a, b);
+    double nrm = 0.0;
+    for (int64_t k = a + threadIdx.x; k < b; k += kRedBS) {
+        double acc[kIRMaxOut];
+#pragma unroll
+        for (int o = 0; o < kIRMaxOut; ++o) acc[o] = 0.0;
+        for (int i = 0; i < nin; ++i) {
+            const double v = (double)pin[i][k];
+#pragma unroll
+            for (int o = 0; o < kIRMaxOut; ++o)
+                if (o < nout) acc[o] += c[i * nout + o] * v;
+        }
+#pragma unroll
+        for (int o = 0; o < kIRMaxOut; ++o)
+            if (o < nout) {
+                const TX st = (TX)acc[o];
+                const_cast<TX *>(pin[o])[k] = st;
+                if (o == nout - 1) nrm += (double)st * (double)st;
+            }
+    }
+    const double sm = block_sum_any<kRedBS>(nrm, red);
+    if (threadIdx.x == 0) norm_part[blockIdx.x] = sm;
 }
 
 __global__ void k_scale(void *y, int64_t n, double f, int is_f32) {
@@ -438,7 +478,85 @@ struct Work {
     double *sig2 = nullptr, *gamma = nullptr, *raw = nullptr, *alpha = nullptr, *beta = nullptr;
     double *partials = nullptr, *tri = nullptr, *triwork = nullptr, *coef = nullptr;
     double *gram = nullptr;      // (m+1) x (m+1) Gram matrix of the stored vectors (reorth = 3)
+    double *rcoef = nullptr;     // implicit-restart combination coefficients
 };
+
+// ------------------------------------------------------- implicit restart --
+// Host side of the implicitly restarted Lanczos method (Sorensen's exact-shift
+// restart, as in ARPACK): T (m x m tridiagonal: alpha, beta[0..m-2]) gets the
+// m - k largest of its eigenvalues applied as shifts, each by one QR step
+// T - mu I = Q R, T <- R Q + mu I = Q^T T Q, with Q accumulated.  The leading
+// k x k block of the result is again tridiagonal, and the new basis is
+// V Q[:, 0..k), the new residual V Q[:, k] T+[k, k-1] + f Q[m-1, k-1].
+
+// number of eigenvalues of the tridiagonal (a, b) below x (Sturm sequence)
+static int sturm_count(const std::vector<double> &a, const std::vector<double> &b, int m, double x) {
+    int cnt = 0;
+    double d = a[0] - x;
+    if (d < 0) ++cnt;
+    for (int i = 1; i < m; ++i) {
+        const double dd = (d == 0.0) ? 1e-300 : d;
+        d = a[i] - x - b[i - 1] * b[i - 1] / dd;
+        if (d < 0) ++cnt;
+    }
+    return cnt;
+}
+
+// eigenvalue number idx (ascending) of the tridiagonal, by bisection
+static double tridiag_eig(const std::vector<double> &a, const std::vector<double> &b, int m, int idx) {
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(a, b, m, mid) > idx) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Shifted QR steps on the dense copy of T; returns T+ (dense) and Q (m x m,
+// row-major).  Rotation G_i acts on coordinates (i, i+1).
+static void ir_shift(std::vector<double> &T, std::vector<double> &Q, int m, const std::vector<double> &shifts) {
+    auto at = [m](std::vector<double> &M, int r, int c) -> double & { return M[(size_t)r * m + c]; };
+    std::vector<double> M((size_t)m * m), cs((size_t)m), sn((size_t)m);
+    for (double mu : shifts) {
+        M = T;
+        for (int i = 0; i < m; ++i) at(M, i, i) -= mu;
+        for (int i = 0; i + 1 < m; ++i) {  // QR of T - mu I: zero M[i+1][i]
+            const double x = at(M, i, i), z = at(M, i + 1, i);
+            const double r = std::hypot(x, z);
+            const double c = r > 0 ? x / r : 1.0, sv = r > 0 ? z / r : 0.0;
+            cs[i] = c;
+            sn[i] = sv;
+            for (int k = 0; k < m; ++k) {
+                const double p = at(M, i, k), q = at(M, i + 1, k);
+                at(M, i, k) = c * p + sv * q;
+                at(M, i + 1, k) = -sv * p + c * q;
+            }
+        }
+        for (int i = 0; i + 1 < m; ++i) {  // T <- G_i^T T G_i, Q <- Q G_i
+            const double c = cs[i], sv = sn[i];
+            for (int k = 0; k < m; ++k) {
+                const double p = at(T, i, k), q = at(T, i + 1, k);
+                at(T, i, k) = c * p + sv * q;
+                at(T, i + 1, k) = -sv * p + c * q;
+            }
+            for (int k = 0; k < m; ++k) {
+                const double p = at(T, k, i), q = at(T, k, i + 1);
+                at(T, k, i) = c * p + sv * q;
+                at(T, k, i + 1) = -sv * p + c * q;
+                const double pq = at(Q, k, i), qq = at(Q, k, i + 1);
+                at(Q, k, i) = c * pq + sv * qq;
+                at(Q, k, i + 1) = -sv * pq + c * qq;
+            }
+        }
+    }
+}
 
 static void fill_defaults(ed_lanczos_opts &o) {
     o.max_iter = 600;
@@ -447,6 +565,7 @@ static void fill_defaults(ed_lanczos_opts &o) {
     o.reorth = 2;
     o.check_every = 4;
     o.refine = 1;
+    o.keep = 0;
 }
 
 static ed_lanczos_opts effective(const ed_lanczos_opts *opts, int64_t D) {
@@ -460,6 +579,9 @@ static ed_lanczos_opts effective(const ed_lanczos_opts *opts, int64_t D) {
     if (!(o.tol > 0.0)) o.tol = 1e-10;
     if (o.reorth < 0 || o.reorth > 3) o.reorth = 2;
     if (o.check_every <= 0) o.check_every = 4;
+    if (o.keep < 0 || o.max_basis > kIRMaxIn - 1) o.keep = 0;
+    if (o.keep > kIRMaxOut - 1) o.keep = kIRMaxOut - 1;
+    if (o.keep >= o.max_basis) o.keep = o.max_basis - 1;
     return o;
 }
 
@@ -485,6 +607,7 @@ static size_t layout(Work &w, char *base, int64_t D, size_t elem, int m, int kma
     w.beta = (double *)c.take((size_t)(m + 2) * sizeof(double));
     w.partials = (double *)c.take((size_t)2 * nv * (size_t)w.nblk * sizeof(double));
     w.gram = (double *)c.take((size_t)(m + 1) * (size_t)(m + 1) * sizeof(double));
+    w.rcoef = (double *)c.take((size_t)kIRMaxIn * kIRMaxOut * sizeof(double));
     w.tri = (double *)c.take((size_t)(m + 8) * sizeof(double));
     w.triwork = (double *)c.take((size_t)(8 + 6 * (m + 2)) * sizeof(double) + (size_t)(m + 2) * sizeof(int) + 64);
     return c.off + 256;
@@ -580,6 +703,84 @@ struct Solver {
     // One eigenpair by restarted Lanczos.  `out` receives the Ritz vector
     // normalised to 1 (it must not be one of the slots).  Returns the status.
     // fresh >= 0: start from the SplitMix64 normal stream `fresh` instead of v0.
+    // Implicit restart keeping k vectors after a full cycle of m steps (slots
+    // kr[0..m] hold S_0..S_m).  All checks come before the in-place rebuild of
+    // the basis; false = not applicable (the caller restarts explicitly).
+    // Returns with alpha/beta/sig2 (and the Gram block) set for continuing at
+    // step k; *breakdown when the kept vectors span an invariant subspace.
+    bool implicit_restart(int m, int k, bool *breakdown) {
+        *breakdown = false;
+        std::vector<double> al((size_t)m), be((size_t)m), sg((size_t)m + 1);
+        ED_HIP(hipMemcpyAsync(al.data(), w.alpha, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+        ED_HIP(hipMemcpyAsync(be.data(), w.beta, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+        ED_HIP(hipMemcpyAsync(sg.data(), w.sig2, (size_t)(m + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        ED_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < m; ++i)
+            if (!std::isfinite(al[i]) || !std::isfinite(be[i]) || !(sg[i] > 0.0)) return false;
+        if (!(sg[m] > 0.0)) return false;
+        std::vector<double> ev((size_t)m), shifts;
+        for (int i = 0; i < m; ++i) ev[i] = tridiag_eig(al, be, m, i);
+        for (int i = k; i < m; ++i) shifts.push_back(ev[i]);
+        std::vector<double> T((size_t)m * m, 0.0), Q((size_t)m * m, 0.0);
+        for (int i = 0; i < m; ++i) {
+            T[(size_t)i * m + i] = al[i];
+            Q[(size_t)i * m + i] = 1.0;
+            if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = be[i];
+        }
+        ir_shift(T, Q, m, shifts);
+        std::vector<double> a2((size_t)k), b2((size_t)std::max(k, 1), 0.0);
+        for (int i = 0; i < k; ++i) {
+            a2[i] = T[(size_t)i * m + i];
+            if (i + 1 < k) b2[i] = 0.5 * (T[(size_t)(i + 1) * m + i] + T[(size_t)i * m + i + 1]);
+        }
+        const double t0 = tridiag_eig(a2, b2, k, 0);
+        if (!(std::fabs(t0 - ev[0]) <= 1e-8 * std::max(1.0, std::fabs(ev[0])))) return false;
+        // inputs S_0..S_m, outputs u_0..u_{k-1} and the new residual f
+        const int nin = m + 1, nout = k + 1;
+        const double tk = T[(size_t)k * m + (k - 1)];
+        std::vector<double> C((size_t)nin * nout, 0.0);
+        for (int l = 0; l < m; ++l) {
+            const double sl = std::sqrt(sg[l]);
+            for (int o = 0; o < k; ++o) C[(size_t)l * nout + o] = Q[(size_t)l * m + o] * sl;
+            C[(size_t)l * nout + k] = Q[(size_t)l * m + k] * sl * tk;
+        }
+        C[(size_t)m * nout + k] = be[m - 1] * std::sqrt(sg[m]) * Q[(size_t)(m - 1) * m + (k - 1)];
+        ED_HIP(hipMemcpyAsync(w.rcoef, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        if (h->prec == ED_FP64)
+            k_restart_combine<double><<<w.nblk, kRedBS, 0, s>>>((const double *const *)w.vp, w.rcoef, nin, nout, h->D,
+                                                               w.partials);
+        else
+            k_restart_combine<float><<<w.nblk, kRedBS, 0, s>>>((const float *const *)w.vp, w.rcoef, nin, nout, h->D,
+                                                              w.partials);
+        ED_LAUNCH_CHECK();
+        k_finalize_dots<<<1, 256, 0, s>>>(w.partials, 1, w.nblk, nullptr, w.raw, nullptr, nullptr, 0);
+        ED_LAUNCH_CHECK();
+        double n2 = 0.0;
+        ED_HIP(hipMemcpyAsync(&n2, w.raw, sizeof(double), hipMemcpyDeviceToHost, s));
+        ED_HIP(hipStreamSynchronize(s));
+        std::vector<double> na((size_t)m + 2, 0.0), nbv((size_t)m + 2, 0.0), ns((size_t)m + 1, 0.0);
+        for (int i = 0; i < k; ++i) {
+            na[i] = a2[i];
+            if (i + 1 < k) nbv[i] = b2[i];
+            ns[i] = 1.0;
+        }
+        const double scale = std::max(1.0, std::fabs(ev[0]));
+        if (!(n2 > (64.0 * 2.220446049250313e-16 * scale) * (64.0 * 2.220446049250313e-16 * scale)))
+            *breakdown = true;
+        nbv[k - 1] = *breakdown ? 0.0 : std::sqrt(n2);
+        ns[k] = *breakdown ? 0.0 : 1.0 / n2;
+        ED_HIP(hipMemcpyAsync(w.alpha, na.data(), na.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        ED_HIP(hipMemcpyAsync(w.beta, nbv.data(), nbv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        ED_HIP(hipMemcpyAsync(w.sig2, ns.data(), ns.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        if (o.reorth == 3) {
+            std::vector<double> G((size_t)(m + 1) * (m + 1), 0.0);
+            for (int i = 0; i < k; ++i) G[(size_t)i * (m + 1) + i] = 1.0;
+            ED_HIP(hipMemcpyAsync(w.gram, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        }
+        ED_HIP(hipStreamSynchronize(s));
+        return true;
+    }
+
     ed_status run(const void *v0, void *out, double *E, ed_info *info, int64_t fresh = -1) {
         const int m = w.m;
         ed_info inf{};
@@ -598,11 +799,14 @@ struct Solver {
         double theta = 0.0, resid = 0.0;
         int jlast = -1;  // number of steps in the current cycle
         const double eps = 2.220446049250313e-16;
+        int jstart = 0;  // first step of the cycle (k after an implicit restart)
         while (true) {
-            k_zero<<<1, 256, 0, s>>>(w.alpha, m + 2);
-            k_zero<<<1, 256, 0, s>>>(w.beta, m + 2);
-            ED_LAUNCH_CHECK();
-            int j = 0;
+            if (jstart == 0) {
+                k_zero<<<1, 256, 0, s>>>(w.alpha, m + 2);
+                k_zero<<<1, 256, 0, s>>>(w.beta, m + 2);
+                ED_LAUNCH_CHECK();
+            }
+            int j = jstart;
             bool cycle_done = false;
             for (; j < m; ++j) {
                 void *Y = kr[j + 1];
@@ -665,6 +869,29 @@ struct Solver {
                 combine(nlock, w.coef, jlast, out);
                 break;
             }
+            bool brk_ir = false;
+            if (o.keep > 0 && nlock == 0 && jlast == m && implicit_restart(m, o.keep, &brk_ir)) {
+                ++inf.restarts;
+                jstart = o.keep;
+                if (brk_ir) {
+                    // the kept vectors span an invariant subspace: finish on them
+                    k_tridiag_lowest<<<1, 256, 0, s>>>(w.alpha, w.beta, jstart, 0.0, w.tri, w.triwork);
+                    ED_LAUNCH_CHECK();
+                    jlast = jstart;
+                    converged = true;
+                    k_ritz_coef<<<1, 256, 0, s>>>(w.tri + 3, w.sig2 + nlock, jlast, w.coef);
+                    ED_LAUNCH_CHECK();
+                    double tv[3];
+                    ED_HIP(hipMemcpyAsync(tv, w.tri, sizeof(tv), hipMemcpyDeviceToHost, s));
+                    ED_HIP(hipStreamSynchronize(s));
+                    theta = tv[0];
+                    resid = 0.0;
+                    combine(nlock, w.coef, jlast, out);
+                    break;
+                }
+                continue;
+            }
+            jstart = 0;
             // restart: psi -> the spare slot, which becomes the new S_0
             void *spare = kr[m];
             combine(nlock, w.coef, jlast, spare);

@@ -49,7 +49,8 @@ class ed_params(ctypes.Structure):
 
 class ed_lanczos_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("max_basis", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("reorth", ctypes.c_int32), ("check_every", ctypes.c_int32), ("refine", ctypes.c_int32)]
+                ("reorth", ctypes.c_int32), ("check_every", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("keep", ctypes.c_int32)]
 
 
 class ed_info(ctypes.Structure):
@@ -126,11 +127,11 @@ def _dev_ptr(t) -> int:
     return t.data_ptr()
 
 
-def options(max_iter=None, max_basis=None, tol=None, reorth=None, check_every=None, refine=None):
+def options(max_iter=None, max_basis=None, tol=None, reorth=None, check_every=None, refine=None, keep=None):
     o = ed_lanczos_opts()
     _lib.ed_lanczos_defaults(ctypes.byref(o))
     for k, v in (("max_iter", max_iter), ("max_basis", max_basis), ("tol", tol), ("reorth", reorth),
-                 ("check_every", check_every), ("refine", refine)):
+                 ("check_every", check_every), ("refine", refine), ("keep", keep)):
         if v is not None:
             setattr(o, k, v)
     return o

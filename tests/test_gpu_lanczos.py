@@ -103,6 +103,34 @@ def test_ground_state_single_read_projections(name, phys, nn, max_basis, prec):
     assert r <= max(10 * info["residual"], 1e-9)
 
 
+@pytest.mark.parametrize("reorth", [2, 3], ids=["cgs2", "single_read"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("name,phys,nn", [
+    ("kan9_45", wl.kanamori(3, 2, 2.3, 0.4, seed=3), (4, 5)),
+    ("hub3x3_45", wl.hubbard(3, 3, 1.0, 4.0), (4, 5)),
+    ("aim8_26", wl.aim(7, 2.0, -1.0, seed=8), (2, 6)),
+], ids=["kan9_45", "hub3x3_45", "aim8_26"])
+def test_ground_state_implicit_restart(name, phys, nn, prec, reorth):
+    """keep = k: exact-shift implicit restarts keep k vectors; the result is the
+    oracle E0 and takes fewer steps than restarting from the Ritz vector alone."""
+    ed = gpu_ed()
+    b, H = build(phys, *nn, prec)
+    sec = sector(phys, *nn)
+    e_ref = orc.lowest_k(sec, 1, tol=1e-14)[0]
+    tol = 1e-10 if prec == 0 else 1e-7
+    v0 = _v0(b.D, prec)
+    psi = torch.empty(b.D, dtype=torch.float64 if prec == 0 else torch.float32, device=DEV)
+    E, info = H.lanczos_ground(v0, ed.options(tol=tol, reorth=reorth, max_basis=14, keep=6, max_iter=4000),
+                               psi=psi)
+    assert info["converged"] == 1 and info["restarts"] > 0, info
+    assert _rel(E, e_ref) <= TOL[prec], (E, e_ref, info)
+    p = psi.double().cpu().numpy()
+    r = np.linalg.norm(sec.spmv(p) - E * p)
+    assert r <= max(10 * info["residual"], 1e-9)
+    _, i0 = H.lanczos_ground(v0, ed.options(tol=tol, reorth=reorth, max_basis=14, keep=0, max_iter=4000))
+    assert info["iters"] <= i0["iters"], (info, i0)
+
+
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 def test_single_read_projections_match_cgs2(prec):
     """Same start vector, same Krylov space: the two orthogonalisation forms
@@ -193,16 +221,18 @@ def test_config3_sectors_vs_golden(nn, prec):
     assert _rel(E, e_ref) <= TOL[prec], (E, e_ref, info)
 
 
-@pytest.mark.parametrize("reorth", [2, 3], ids=["cgs2", "single_read"])
+@pytest.mark.parametrize("solver", [(2, 100, 0), (3, 100, 0), (3, 24, 12)],
+                         ids=["cgs2", "single_read", "single_read_implicit_restart"])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("jp", [True, False], ids=["jp_on", "jp_off"])
-def test_config2_full_size_vs_golden(jp, prec, reorth):
+def test_config2_full_size_vs_golden(jp, prec, solver):
     ed = gpu_ed()
+    reorth, m, keep = solver
     phys, sectors = wl.config(2, jprime=jp)
     e_ref = _golden("cfg2" if jp else "cfg2_jp_off", "7,7")[0]
     b, H = build(phys, 7, 7, prec)
     E, info = H.lanczos_ground(_v0(b.D, prec, wl.start_vector_seed(2)),
-                               ed.options(tol=1e-10 if prec == 0 else 1e-7, max_basis=100, reorth=reorth))
+                               ed.options(tol=1e-10 if prec == 0 else 1e-7, max_basis=m, reorth=reorth, keep=keep))
     assert _rel(E, e_ref) <= TOL[prec], (E, e_ref, info)
 
 
