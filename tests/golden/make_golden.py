@@ -36,9 +36,27 @@ def save(g):
     os.replace(tmp, OUT)
 
 
+def _counted(sec, t0):
+    """The sector's oracle product, printing a progress line every 10 calls
+    (large sectors run for many minutes)."""
+    base = sec.spmv
+    n = [0]
+
+    def spmv(x):
+        y = base(x)
+        n[0] += 1
+        if n[0] % 10 == 0:
+            print("  D=%d: %d products, %.0fs" % (sec.D, n[0], time.time() - t0), flush=True)
+        return y
+    return spmv
+
+
 def sector_e0(phys, nup, ndn, k=1):
     sec = orc.sector_for(phys, nup, ndn)
     t0 = time.time()
+    if sec.D > 1_000_000:
+        print("  D=%d: building the oracle CSR matrix" % sec.D, flush=True)
+        sec.spmv = _counted(sec, t0)
     if sec.D <= 5000:
         ev = np.linalg.eigvalsh(sec.dense())[:k]
         e_l = ev[0]
