@@ -897,6 +897,8 @@ static const Variant kVariants[] = {
     {8, 2, 512, 256, "csx_rr2_rw32_band256", 0, 8},
     {8, 2, 512, 512, "csx_rr2_rw32_band512", 0, 8},
     {8, 4, 512, 256, "csx_rr4_rw32_band256", 0, 8},
+    {8, 2, 1024, 512, "csx_rr2_b1024_rw32_band512", 0, 8},
+    {8, 2, 1024, 256, "csx_rr2_b1024_rw64_band256", 0, 8},
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static constexpr int64_t kDynBudget = 163840 - 8192;  // LDS left for the staged x block
@@ -1146,9 +1148,8 @@ static int cs_xmax(const ed_ham_s *h) {
     return h->xl_max <= 4 ? 4 : (h->xl_max <= 8 ? 8 : 0);
 }
 
-template <typename TX, typename TA, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX>
+template <typename TX, typename TA, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX, int BS>
 static int64_t launch_cs_k(ed_ham_s *h, ApplyArgs<TX, TA> a, int rw, hipStream_t s) {
-    constexpr int BS = 512;
     int nwin = 0, wmax = 0;
     a.win = windows_for(h, (int64_t)BS, &nwin, &wmax);
     a.nwin = nwin;
@@ -1160,21 +1161,24 @@ static int64_t launch_cs_k(ed_ham_s *h, ApplyArgs<TX, TA> a, int rw, hipStream_t
     return G * nwin;
 }
 
-template <typename TX, typename TA, int RR, int MODE, bool UPX, int KMAX>
+template <typename TX, typename TA, int RR, int MODE, bool UPX, int KMAX, int BS>
 static int64_t launch_cs_km(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
     const int nm = cs_nmv(h), xm = cs_xmax(h);
-    if (nm == 0) return launch_cs_k<TX, TA, RR, KMAX, 0, 0, MODE, UPX>(h, a, rw, s);
-    if (nm == 8 && xm == 4) return launch_cs_k<TX, TA, RR, KMAX, 8, 4, MODE, UPX>(h, a, rw, s);
-    if (nm == 8 && xm == 8) return launch_cs_k<TX, TA, RR, KMAX, 8, 8, MODE, UPX>(h, a, rw, s);
+    if (nm == 0) return launch_cs_k<TX, TA, RR, KMAX, 0, 0, MODE, UPX, BS>(h, a, rw, s);
+    if (nm == 8 && xm == 4) return launch_cs_k<TX, TA, RR, KMAX, 8, 4, MODE, UPX, BS>(h, a, rw, s);
+    if (nm == 8 && xm == 8) return launch_cs_k<TX, TA, RR, KMAX, 8, 8, MODE, UPX, BS>(h, a, rw, s);
     fail(ED_EINVAL, "column-stationary schedule does not fit this Hamiltonian");
 }
 
-template <typename TX, typename TA, int RR, int MODE, bool UPX>
+// BS threads own a window of BS down ranks
+template <typename TX, typename TA, int RR, int MODE, bool UPX, int BS = 512>
 static int64_t launch_cs(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int rw, hipStream_t s) {
     const int km = cs_kmax(h);
-    if (km == 8) return launch_cs_km<TX, TA, RR, MODE, UPX, 8>(h, a, rw, s);
-    if (km == 16) return launch_cs_km<TX, TA, RR, MODE, UPX, 16>(h, a, rw, s);
-    if (km == 32) return launch_cs_km<TX, TA, RR, MODE, UPX, 32>(h, a, rw, s);
+    if (km == 8) return launch_cs_km<TX, TA, RR, MODE, UPX, 8, BS>(h, a, rw, s);
+    if (km == 16) return launch_cs_km<TX, TA, RR, MODE, UPX, 16, BS>(h, a, rw, s);
+    if constexpr (BS <= 512) {
+        if (km == 32) return launch_cs_km<TX, TA, RR, MODE, UPX, 32, BS>(h, a, rw, s);
+    }
     fail(ED_EINVAL, "column-stationary schedule does not fit this Hamiltonian");
 }
 
@@ -1197,6 +1201,14 @@ static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipSt
         case 12:
         case 13: launch_cs<TX, TA, 2, 0, false>(h, a, 32, s); launch_upb<TX, TA, true>(a, V.band, V.rw, s); break;
         case 14: launch_cs<TX, TA, 4, 0, false>(h, a, 32, s); launch_upb<TX, TA, true>(a, V.band, V.rw, s); break;
+        case 15:
+            launch_cs<TX, TA, 2, 0, false, 1024>(h, a, 32, s);
+            launch_upb<TX, TA, true>(a, V.band, V.rw, s);
+            break;
+        case 16:
+            launch_cs<TX, TA, 2, 0, false, 1024>(h, a, 64, s);
+            launch_upb<TX, TA, true>(a, V.band, V.rw, s);
+            break;
         default: fail(ED_EINVAL, "bad apply variant %d", v);
     }
 }
@@ -1210,6 +1222,7 @@ static bool variant_fits(const ed_ham_s *h, int v, size_t elem) {
     if (V.kind == 6 && (!h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->koff > 4)) return false;
     if (V.kind == 8 && (h->sp[0].nnz == 0 || cs_kmax(h) == 0 || cs_nmv(h) < 0 || (h->nx > 0 && cs_xmax(h) == 0)))
         return false;
+    if (V.kind == 8 && V.BS > 512 && cs_kmax(h) > 16) return false;
     return true;
 }
 
