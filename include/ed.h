@@ -250,7 +250,9 @@ ed_status ed_arnoldi_lowest(ed_ham_t h, int k, const ed_lanczos_opts *opts, cons
  * stream seed + i).  E0: HOST [nsec] lowest eigenvalue per sector (FP64
  * Rayleigh quotient of the Ritz vector when opts->refine).  info: HOST [nsec]
  * or NULL.  ws: DEVICE workspace of at least ed_batched_workspace_bytes.
- * Synchronous.  ED_ENOCONV if some sector hit max_iter (all E0 still written). */
+ * Synchronous.  ED_ENOCONV if some sector hit max_iter (all E0 still written).
+ * The batch restarts explicitly and runs CGS2 (opts->keep is ignored and
+ * reorth = 3 runs as 2). */
 ed_status ed_batched_workspace_bytes(int nsec, const ed_ham_t *hs, const ed_lanczos_opts *opts,
                                      size_t *bytes);
 ed_status ed_lanczos_ground_batched(int nsec, const ed_ham_t *hs, const ed_lanczos_opts *opts,

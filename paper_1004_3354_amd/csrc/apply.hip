@@ -292,132 +292,7 @@ __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
     }
 }
 
-// Column-stationary kernel.  A workgroup owns one window of down ranks (at
-// most BS*CPT of them, a run of states sharing their top bits) and streams over
-// `rw` consecutive rows.  Each thread owns CPT columns and keeps everything
-// that depends only on the column in registers for the whole row stream: its
-// down-spin hop entries (target as a window-local LDS index, or the global
-// rank when the hop leaves the window, and signed amplitude), its one-spin
-// diagonal piece and bit string, and its entries of the down move tables of
-// the four-fermion terms.  Per row only independent gathers remain: the row
-// window (double-buffered in LDS), the up-spin partner rows and the
-// four-fermion partners, so many loads are in flight per wave.
-
-template <typename TX, typename TA, int BS, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX>
-__global__ __launch_bounds__(BS) void k_cs(ApplyArgs<TX, TA> a, int rw) {
-    // RR rows are processed per step (all their gathers in flight together);
-    // LDS holds two buffers of RR row windows.
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[2][BS / 64];
-    const int wm = a.wmax;
-    TX *bufs = reinterpret_cast<TX *>(smem_raw);
-    const int64_t ddn = a.ddn;
-    const int nwin = a.nwin;
-    const int64_t G = (a.dup + rw - 1) / rw;
-    const int64_t t = xcd_remap(blockIdx.x, G * nwin);
-    const int64_t g = t / nwin;
-    const int wi = (int)(t - g * nwin);
-    const int64_t u0 = g * rw;
-    const int nr = (int)((a.dup - u0) < rw ? (a.dup - u0) : rw);
-    const int32_t w0 = a.win[wi].x, wl = a.win[wi].y;
-
-    const int32_t li = (int32_t)threadIdx.x;
-    const bool act = li < wl;
-    const int64_t d = (int64_t)w0 + (act ? li : 0);
-    const int32_t ld = (int32_t)(d - w0);
-    int32_t lt[KMAX];
-    TA sa[KMAX];
-    {
-        const int32_t o = a.dn_off[d], n = a.dn_off[d + 1] - o;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const bool ok = k < n;
-            const int32_t tg = ok ? a.dn_tgt[o + k] : (int32_t)d;
-            const int32_t l = tg - w0;
-            lt[k] = ((uint32_t)l < (uint32_t)wl) ? l : (-1 - tg);
-            sa[k] = ok ? a.dn_sa[o + k] : (TA)0;
-        }
-    }
-    const TA edn = a.dn_e[d];
-    const uint32_t sdn = a.dn_st[d], cdn = a.dn_c[d];
-    int32_t mvd[NMV > 0 ? NMV : 1];
-#pragma unroll
-    for (int q = 0; q < NMV; ++q) mvd[q] = q < a.nmv_dn ? a.dn_mv[(int64_t)q * ddn + d] : -1;
-
-    // stage the first RR rows
-#pragma unroll
-    for (int rr = 0; rr < RR; ++rr)
-        if (rr < nr && act) bufs[rr * wm + li] = a.x[(u0 + rr) * ddn + w0 + li];
-    __syncthreads();
-
-    double p0 = 0.0, p1 = 0.0;
-    int step = 0;
-    for (int r0 = 0; r0 < nr; r0 += RR, ++step) {
-        TX *cur = bufs + ((step & 1) ? RR * wm : 0);
-        TX *nxt = bufs + ((step & 1) ? 0 : RR * wm);
-        TX pf[RR];
-#pragma unroll
-        for (int rr = 0; rr < RR; ++rr) {
-            const int rn = r0 + RR + rr;
-            pf[rr] = (rn < nr && act) ? a.x[(u0 + rn) * ddn + w0 + li] : (TX)0;
-        }
-        TA acc[RR], xv[RR];
-#pragma unroll
-        for (int rr = 0; rr < RR; ++rr) {
-            const int r = r0 + rr;
-            const int64_t u = u0 + (r < nr ? r : 0);
-            const TX *xrow = a.x + u * ddn;
-            xv[rr] = (TA)cur[rr * wm + ld];
-            acc[rr] = (a.up_e[u] + edn + cross_term(a, a.up_st[u], sdn, a.up_c[u], cdn)) * xv[rr];
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                const int32_t l = lt[k];
-                const TA v = l >= 0 ? (TA)cur[rr * wm + l] : (TA)xrow[-1 - l];
-                acc[rr] += sa[k] * v;
-            }
-        }
-        if (act) {
-#pragma unroll
-            for (int rr = 0; rr < RR; ++rr) {
-                const int r = r0 + rr;
-                if (r >= nr) break;
-                if constexpr (MODE == 0) {
-                    a.y[(u0 + r) * ddn + d] = (TX)acc[rr];
-                } else if constexpr (MODE == 1) {
-                    p0 += (double)xv[rr] * (double)acc[rr];
-                    p1 += (double)xv[rr] * (double)xv[rr];
-                } else {
-                    const double df = (double)acc[rr] - a.theta * (double)xv[rr];
-                    p0 += df * df;
-                }
-            }
-#pragma unroll
-            for (int rr = 0; rr < RR; ++rr) nxt[rr * wm + li] = pf[rr];
-        }
-        __syncthreads();
-    }
-    if constexpr (MODE != 0) {
-        const double s0 = block_sum<BS>(p0, red[0]);
-        const double s1 = block_sum<BS>(p1, red[1]);
-        if (threadIdx.x == 0) {
-            a.partials[2 * (int64_t)blockIdx.x] = s0;
-            a.partials[2 * (int64_t)blockIdx.x + 1] = s1;
-        }
-    }
-}
-
-// ------------------------------------------------------ transposed tiles --
-// Row-tile kernel with the tile transposed in LDS.  A workgroup owns R rows and
-// one window of down ranks; LDS holds the tile column-major (xs[l*R + r]), so
-// one LDS read returns a column's values for all R rows and every down-spin
-// hop entry serves R output elements.  Each thread owns four consecutive
-// columns: x rows, partner rows and y move as 16-byte accesses (rows need only
-// element alignment), and the down-spin entries of its four states come from
-// the four-state packed ELL in one 16-byte load.  Thread chunks start at a
-// multiple of 256 columns so that a wave covers exactly one ELL slice.
-// UPX = true: full product.  UPX = false: everything but H_up (x) 1 (the row
-// pass of the two-pass schedule).  NTY: y is stored non-temporally (kept out of
-// the caches so that x stays resident).
+// 4-vectors at element alignment, R-vectors, and their element access
 template <typename TX>
 struct V4 {
     typedef TX t __attribute__((ext_vector_type(4), aligned(sizeof(TX))));
@@ -457,6 +332,148 @@ template <typename TX>
 __device__ __forceinline__ typename V4<TX>::t ld4(const TX *p) {
     return *reinterpret_cast<const typename V4<TX>::t *>(p);
 }
+
+// Column-stationary kernel.  A workgroup owns one window of down ranks (at
+// most BS*CPT of them, a run of states sharing their top bits) and streams over
+// `rw` consecutive rows.  Each thread owns CPT columns and keeps everything
+// that depends only on the column in registers for the whole row stream: its
+// down-spin hop entries (target as a window-local LDS index, or the global
+// rank when the hop leaves the window, and signed amplitude), its one-spin
+// diagonal piece and bit string, and its entries of the down move tables of
+// the four-fermion terms.  Per row only independent gathers remain: the row
+// window (double-buffered in LDS), the up-spin partner rows and the
+// four-fermion partners, so many loads are in flight per wave.
+
+template <typename TX, typename TA, int BS, int RR, int KMAX, int NMV, int XMAX, int MODE, bool UPX>
+__global__ __launch_bounds__(BS) void k_cs(ApplyArgs<TX, TA> a, int rw) {
+    // RR rows are processed per step (all their gathers in flight together);
+    // LDS holds two buffers of RR row windows, transposed (column l of the step
+    // at l * RR), so one LDS read serves the RR rows and is never merged with
+    // the scalar memory read of an out-of-window partner into one
+    // generic-address load.
+    using RVt = typename RV<TX, RR>::t;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[2][BS / 64];
+    const int wm = a.wmax;
+    TX *bufs = reinterpret_cast<TX *>(smem_raw);
+    const int64_t ddn = a.ddn;
+    const int nwin = a.nwin;
+    const int64_t G = (a.dup + rw - 1) / rw;
+    const int64_t t = xcd_remap(blockIdx.x, G * nwin);
+    const int64_t g = t / nwin;
+    const int wi = (int)(t - g * nwin);
+    const int64_t u0 = g * rw;
+    const int nr = (int)((a.dup - u0) < rw ? (a.dup - u0) : rw);
+    const int32_t w0 = a.win[wi].x, wl = a.win[wi].y;
+
+    const int32_t li = (int32_t)threadIdx.x;
+    const bool act = li < wl;
+    const int64_t d = (int64_t)w0 + (act ? li : 0);
+    const int32_t ld = (int32_t)(d - w0);
+    int32_t lt[KMAX];
+    TA sa[KMAX];
+    {
+        const int32_t o = a.dn_off[d], n = a.dn_off[d + 1] - o;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const bool ok = k < n;
+            const int32_t tg = ok ? a.dn_tgt[o + k] : (int32_t)d;
+            const int32_t l = tg - w0;
+            lt[k] = ((uint32_t)l < (uint32_t)wl) ? l : (-1 - tg);
+            sa[k] = ok ? a.dn_sa[o + k] : (TA)0;
+        }
+    }
+    const TA edn = a.dn_e[d];
+    const uint32_t sdn = a.dn_st[d], cdn = a.dn_c[d];
+    int32_t mvd[NMV > 0 ? NMV : 1];
+#pragma unroll
+    for (int q = 0; q < NMV; ++q) mvd[q] = q < a.nmv_dn ? a.dn_mv[(int64_t)q * ddn + d] : -1;
+
+    // stage the first RR rows
+    if (act) {
+        RVt o;
+#pragma unroll
+        for (int rr = 0; rr < RR; ++rr) o[rr] = rr < nr ? a.x[(u0 + rr) * ddn + w0 + li] : (TX)0;
+        *reinterpret_cast<RVt *>(bufs + (int64_t)li * RR) = o;
+    }
+    __syncthreads();
+
+    double p0 = 0.0, p1 = 0.0;
+    int step = 0;
+    for (int r0 = 0; r0 < nr; r0 += RR, ++step) {
+        TX *cur = bufs + ((step & 1) ? RR * wm : 0);
+        TX *nxt = bufs + ((step & 1) ? 0 : RR * wm);
+        TX pf[RR];
+#pragma unroll
+        for (int rr = 0; rr < RR; ++rr) {
+            const int rn = r0 + RR + rr;
+            pf[rr] = (rn < nr && act) ? a.x[(u0 + rn) * ddn + w0 + li] : (TX)0;
+        }
+        TA acc[RR], xv[RR];
+        const RVt self = *reinterpret_cast<const RVt *>(cur + (int64_t)ld * RR);
+#pragma unroll
+        for (int rr = 0; rr < RR; ++rr) {
+            const int r = r0 + rr;
+            const int64_t u = u0 + (r < nr ? r : 0);
+            xv[rr] = (TA)self[rr];
+            acc[rr] = (a.up_e[u] + edn + cross_term(a, a.up_st[u], sdn, a.up_c[u], cdn)) * xv[rr];
+        }
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int32_t l = lt[k];
+            const bool in = l >= 0;
+            const RVt w = *reinterpret_cast<const RVt *>(cur + (int64_t)(in ? l : 0) * RR);
+#pragma unroll
+            for (int rr = 0; rr < RR; ++rr) {
+                TA v = (TA)w[rr];
+                if (!in) v = (TA)a.x[(u0 + (r0 + rr < nr ? r0 + rr : 0)) * ddn + (-1 - l)];
+                acc[rr] += sa[k] * v;
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int rr = 0; rr < RR; ++rr) {
+                const int r = r0 + rr;
+                if (r >= nr) break;
+                if constexpr (MODE == 0) {
+                    a.y[(u0 + r) * ddn + d] = (TX)acc[rr];
+                } else if constexpr (MODE == 1) {
+                    p0 += (double)xv[rr] * (double)acc[rr];
+                    p1 += (double)xv[rr] * (double)xv[rr];
+                } else {
+                    const double df = (double)acc[rr] - a.theta * (double)xv[rr];
+                    p0 += df * df;
+                }
+            }
+            RVt o;
+#pragma unroll
+            for (int rr = 0; rr < RR; ++rr) o[rr] = pf[rr];
+            *reinterpret_cast<RVt *>(nxt + (int64_t)li * RR) = o;
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE != 0) {
+        const double s0 = block_sum<BS>(p0, red[0]);
+        const double s1 = block_sum<BS>(p1, red[1]);
+        if (threadIdx.x == 0) {
+            a.partials[2 * (int64_t)blockIdx.x] = s0;
+            a.partials[2 * (int64_t)blockIdx.x + 1] = s1;
+        }
+    }
+}
+
+// ------------------------------------------------------ transposed tiles --
+// Row-tile kernel with the tile transposed in LDS.  A workgroup owns R rows and
+// one window of down ranks; LDS holds the tile column-major (xs[l*R + r]), so
+// one LDS read returns a column's values for all R rows and every down-spin
+// hop entry serves R output elements.  Each thread owns four consecutive
+// columns: x rows, partner rows and y move as 16-byte accesses (rows need only
+// element alignment), and the down-spin entries of its four states come from
+// the four-state packed ELL in one 16-byte load.  Thread chunks start at a
+// multiple of 256 columns so that a wave covers exactly one ELL slice.
+// UPX = true: full product.  UPX = false: everything but H_up (x) 1 (the row
+// pass of the two-pass schedule).  NTY: y is stored non-temporally (kept out of
+// the caches so that x stays resident).
 
 // cross term with the per-site U values and the 4^koff table taken from LDS
 // copies (the kernels that use it require koff <= 4)
