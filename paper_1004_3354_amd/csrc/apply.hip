@@ -228,15 +228,12 @@ __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
                 const int nxr = xe[r] - xb[r];
 #pragma unroll 2
                 for (int k = 0; k < nxr; ++k) {
-                    // the moves act on the lowest (impurity) bits, so the source row is
-                    // usually one of the staged rows and the column inside the window
+                    // partner rows are nearby rows (L2-resident); read from memory
+                    // (a select between an LDS and a memory address would become
+                    // one generic-address load)
                     const int32_t m = pick<8>(mvd, x_tab[r][k]);
                     const int64_t c = m >= 0 ? (int64_t)(m >> 1) : d;
-                    const int32_t rs = x_src[r][k] - (int32_t)u0;
-                    const int32_t lc = (int32_t)(c - w0);
-                    TA v;
-                    if ((uint32_t)rs < (uint32_t)nr && (uint32_t)lc < (uint32_t)wl) v = (TA)xs[rs * wl + lc];
-                    else v = (TA)a.x[(int64_t)x_src[r][k] * ddn + c];
+                    TA v = (TA)a.x[(int64_t)x_src[r][k] * ddn + c];
                     v = m >= 0 ? ((m & 1) ? -v : v) : (TA)0;
                     acc[r] += x_amp[r][k] * v;
                 }
@@ -657,21 +654,40 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
             int p[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) p[r] = 0;
+            // packed move words of the four columns (one 16-byte load for all moves)
+            uint32_t mvw[4] = {0u, 0u, 0u, 0u};
+            if (a.dn_mvp) {
+                if constexpr (FULL) {
+                    const uint4 t4 = *reinterpret_cast<const uint4 *>(a.dn_mvp + c);
+                    mvw[0] = t4.x; mvw[1] = t4.y; mvw[2] = t4.z; mvw[3] = t4.w;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) mvw[j] = c + j < ddn ? a.dn_mvp[c + j] : 0u;
+                }
+            }
             for (int q = 0; q < a.nmv_dn; ++q) {
                 bool any = false;
 #pragma unroll
                 for (int r = 0; r < R; ++r) any |= (p[r] < nxl[r] && x_tab[r][p[r]] == q);
                 if (!any) continue;
                 int32_t m[4];
-                const int32_t *mp = a.dn_mv + (int64_t)q * ddn + c;
-                if constexpr (FULL) {
-                    int32_t tmp[4];
-                    __builtin_memcpy(tmp, mp, 16);
+                if (a.dn_mvp) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) m[j] = tmp[j];
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t f = (mvw[j] >> (5 * q)) & 31u;
+                        m[j] = (f & 16u) ? (int32_t)(((c + j + (int64_t)(f & 7u) - 4) << 1) | ((f >> 3) & 1u)) : -1;
+                    }
                 } else {
+                    const int32_t *mp = a.dn_mv + (int64_t)q * ddn + c;
+                    if constexpr (FULL) {
+                        int32_t tmp[4];
+                        __builtin_memcpy(tmp, mp, 16);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) m[j] = c + j < ddn ? mp[j] : -1;
+                        for (int j = 0; j < 4; ++j) m[j] = tmp[j];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) m[j] = c + j < ddn ? mp[j] : -1;
+                    }
                 }
                 int32_t col[4];
 #pragma unroll
@@ -832,6 +848,16 @@ __global__ __launch_bounds__(BS) void k_upb(ApplyArgs<TX, TA> a, int64_t band, i
         if constexpr (XT) {
             // four-fermion terms; each row's list is ordered by down move, so
             // a move table entry is loaded once for the RB rows
+            uint32_t mvw[4] = {0u, 0u, 0u, 0u};
+            if (a.dn_mvp) {
+                if (full) {
+                    const uint4 t4 = *reinterpret_cast<const uint4 *>(a.dn_mvp + c);
+                    mvw[0] = t4.x; mvw[1] = t4.y; mvw[2] = t4.z; mvw[3] = t4.w;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) mvw[j] = c + j < ddn ? a.dn_mvp[c + j] : 0u;
+                }
+            }
             int p[RB], pe[RB];
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) {
@@ -845,15 +871,23 @@ __global__ __launch_bounds__(BS) void k_upb(ApplyArgs<TX, TA> a, int64_t band, i
                 for (int rr = 0; rr < RB; ++rr) hit |= (p[rr] < pe[rr] && a.xl_tab[p[rr]] == q);
                 if (!hit) continue;
                 int32_t m[4];
-                const int32_t *mp = a.dn_mv + (int64_t)q * ddn + c;
-                if (full) {
-                    int32_t tmp[4];
-                    __builtin_memcpy(tmp, mp, 16);
+                if (a.dn_mvp) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) m[j] = tmp[j];
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t f = (mvw[j] >> (5 * q)) & 31u;
+                        m[j] = (f & 16u) ? (int32_t)(((c + j + (int64_t)(f & 7u) - 4) << 1) | ((f >> 3) & 1u)) : -1;
+                    }
                 } else {
+                    const int32_t *mp = a.dn_mv + (int64_t)q * ddn + c;
+                    if (full) {
+                        int32_t tmp[4];
+                        __builtin_memcpy(tmp, mp, 16);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) m[j] = c + j < ddn ? mp[j] : -1;
+                        for (int j = 0; j < 4; ++j) m[j] = tmp[j];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) m[j] = c + j < ddn ? mp[j] : -1;
+                    }
                 }
                 int64_t col[4];
 #pragma unroll
@@ -1015,6 +1049,7 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.dn_st = Dn.states.as<uint32_t>();
     a.dn_c = Dn.cidx.as<uint8_t>();
     a.dn_mv = Dn.mv.as<int32_t>();
+    a.dn_mvp = Dn.mvp_ok ? Dn.mvp.as<uint32_t>() : nullptr;
     a.umode = h->umode;
     a.umask = h->umask;
     a.U0 = h->U0;
@@ -1064,6 +1099,7 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.dn_st = Dn.states.as<uint32_t>();
     a.dn_c = Dn.cidx.as<uint8_t>();
     a.dn_mv = Dn.mv.as<int32_t>();
+    a.dn_mvp = Dn.mvp_ok ? Dn.mvp.as<uint32_t>() : nullptr;
     a.umode = h->umode;
     a.umask = h->umask;
     a.U0 = (float)h->U0;

@@ -144,6 +144,10 @@ struct SpinTab {
     int nmv = 0;              // number of move tables
     DevMem mv;                // int32 [nmv][dim] (target << 1 | sign bit) or -1
     std::vector<int> mv_src, mv_dst;  // move q: electron src -> dst
+    // down spin, when every move shifts the rank by -4..3: all moves of a state
+    // in one word, 5 bits per move (valid << 4 | sign << 3 | shift + 4)
+    bool mvp_ok = false;
+    DevMem mvp;                        // uint32 [dim]
 };
 
 // Four-fermion term in factorised form: output (u, d) pulls x[up_mv(u), dn_mv(d)].
@@ -226,6 +230,7 @@ struct ApplyArgs {
     const uint32_t *dn_st;
     const uint8_t *dn_c;
     const int32_t *dn_mv;
+    const uint32_t *dn_mvp;  // packed down move words, or nullptr
     // cross term
     int umode;
     uint32_t umask;

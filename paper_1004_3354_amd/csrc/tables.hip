@@ -511,6 +511,31 @@ static void build_xterms(ed_ham_s *h, const ed_params *p) {
             ED_LAUNCH_CHECK();
         }
     }
+    // down spin: all move tables packed into one word per state when every move
+    // shifts the rank by -4..3 (moves on the lowest sites): 5 bits per move,
+    // valid << 4 | sign << 3 | (shift + 4)
+    {
+        SpinTab &t = h->sp[1];
+        t.mvp_ok = false;
+        if (t.nmv > 0 && t.nmv <= 6 && t.dim > 0) {
+            std::vector<int32_t> mv((size_t)t.nmv * t.dim);
+            ED_HIP(hipMemcpy(mv.data(), t.mv.p, mv.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+            std::vector<uint32_t> w((size_t)t.dim, 0u);
+            bool ok = true;
+            for (int q = 0; q < t.nmv && ok; ++q)
+                for (int64_t d = 0; d < t.dim; ++d) {
+                    const int32_t m = mv[(size_t)q * t.dim + d];
+                    if (m < 0) continue;
+                    const int64_t sh = (int64_t)(m >> 1) - d;
+                    if (sh < -4 || sh > 3) { ok = false; break; }
+                    w[d] |= (16u | ((uint32_t)(m & 1) << 3) | (uint32_t)(sh + 4)) << (5 * q);
+                }
+            if (ok) {
+                upload(t.mvp, w);
+                t.mvp_ok = true;
+            }
+        }
+    }
     std::vector<XTermDev<double>> x64;
     std::vector<XTermDev<float>> x32;
     for (auto &x : h->xterms) {
