@@ -30,7 +30,7 @@
  * by ed_last_error().  ED_EINVAL: bad argument (detailed below per call);
  * ED_ENOMEM: tables or workspace do not fit; ED_EDEVICE: a HIP runtime error;
  * ED_ENOCONV: iteration limit reached (best estimates are still written);
- * ED_EUNSUPPORTED: a valid model this build has no kernel for.
+ * ED_EUNSUPPORTED: a valid model the library has no kernel for.
  */
 #ifndef ED_H
 #define ED_H

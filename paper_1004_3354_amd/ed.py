@@ -295,7 +295,7 @@ def lanczos_ground_batched(hams: Sequence[Hamiltonian], opts=None, seed: int = 0
                            stream=None, allow_noconv=False):
     import torch
     if not hasattr(_lib, "ed_lanczos_ground_batched"):
-        raise EDError(ED_EUNSUPPORTED, "batched Lanczos not in this build")
+        raise EDError(ED_EUNSUPPORTED, "the library has no batched Lanczos entry point")
     o = opts if opts is not None else options()
     n = len(hams)
     hs = (_p * n)(*[h._h for h in hams])
