@@ -337,6 +337,19 @@ def main():
             log("N_s=18 FP32 H.v: %.3f ms, %.1f GB/s" % (e18 / k18 * 1e3, g18))
             del x, y, H18, b18
             torch.cuda.empty_cache()
+            if torch.cuda.mem_get_info()[0] > 48e9:
+                _, _, b18, H18, _ = setup(4, ed.ED_FP64)
+                x = torch.empty(b18.D, dtype=torch.float64, device="cuda")
+                y = torch.empty_like(x)
+                ed.fill_random(x, 12345, 0)
+                w64, e64 = timed_applies(H18, x, y, k18, 2)
+                g64 = 16.0 * b18.D * k18 / e64 / 1e9
+                ns18["fp64"] = {"ms_per_apply": round(e64 / k18 * 1e3, 4), "gbps": round(g64, 1),
+                                "frac": round(g64 / HBM_PEAK_GBS, 4),
+                                "schedule": ed.variant_name(H18.current_variant())}
+                log("N_s=18 FP64 H.v: %.3f ms, %.1f GB/s" % (e64 / k18 * 1e3, g64))
+                del x, y, H18, b18
+                torch.cuda.empty_cache()
 
     # ---- time to E0, FP32-mixed vs FP64, same start vector and target
     e0 = e0_cgs2 = None
