@@ -180,6 +180,59 @@ def time_to_e0(cfg, precs, max_basis, tol, seed_idx, reorth=3, keep=0):
     return out
 
 
+def green_bench(cfg=2, m=100, beta=10.0):
+    """Impurity Green function of Eq. 3 (spin up, site 0 = the first impurity
+    orbital) at the N_s = 15 workload: ground state first (not timed), then the
+    timed part: c+ and c applied to it, an m-step Lanczos in each neighbouring
+    sector and the continued fractions at 64 Matsubara points.  Runs: FP32 and
+    FP64 with full reorthogonalisation (both projections per basis read), and
+    FP32 with the plain three-term recurrence (no reorthogonalisation); each is
+    compared with an FP64 run of 2m levels (the truncation reference)."""
+    import numpy as np
+    import torch
+    from paper_1004_3354_amd import ed, models, workloads as wl
+    out = {"m": m, "spin": 0, "site": 0, "n_matsubara": 64, "beta": beta}
+    z = 1j * np.pi * (2 * np.arange(64) + 1) / beta
+    gref = None
+    for key, prec, reorth, mm in (("fp64_reference", ed.ED_FP64, 3, 2 * m), ("fp64", ed.ED_FP64, 3, m),
+                                  ("fp32_mixed", ed.ED_FP32, 3, m), ("fp32_mixed_no_reorth", ed.ED_FP32, 0, m)):
+        phys, nn, b, H, _ = setup(cfg, prec)
+        dt = torch.float64 if prec == ed.ED_FP64 else torch.float32
+        v0 = torch.empty(b.D, dtype=dt, device="cuda")
+        ed.fill_random(v0, wl.start_vector_seed(cfg), 1)
+        psi = torch.empty_like(v0)
+        e0, _ = H.lanczos_ground(v0, ed.options(tol=1e-7, max_basis=16, keep=8, reorth=3), psi=psi,
+                                 allow_noconv=True)
+        del v0
+        bp, bm = ed.Basis(phys["Ns"], nn[0] + 1, nn[1]), ed.Basis(phys["Ns"], nn[0] - 1, nn[1])
+        Hp = ed.Hamiltonian(models.params_from_model(phys), bp, prec)
+        Hm = ed.Hamiltonian(models.params_from_model(phys), bm, prec)
+        opts = ed.options(reorth=reorth, max_basis=mm)
+        ws = torch.empty(max(Hp.workspace_bytes(opts, 1), Hm.workspace_bytes(opts, 1)), dtype=torch.uint8,
+                         device="cuda")
+        for Hx in (Hp, Hm):   # tune the apply schedules outside the timed region
+            t = ws[: Hx.D * psi.element_size()].view(dt)
+            ed.fill_random(t, 1, 0)
+            Hx.apply(t, ws[Hx.D * psi.element_size(): 2 * Hx.D * psi.element_size()].view(dt))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, info = ed.green_function(H, e0, psi, Hp, Hm, 0, 0, z, m=mm, opts=opts, ws=ws)
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        out[key] = {"seconds": round(dt_s, 4), "reorth": reorth, "E0": e0,
+                    "weights": {k: v["weight"] for k, v in info.items()},
+                    "steps": {k: v["steps"] for k, v in info.items()}}
+        if gref is None:
+            gref = g
+        else:
+            out[key]["max_rel_dev_vs_reference"] = float(np.max(np.abs(g - gref)) / np.max(np.abs(gref)))
+        log("Green function %s: %.3f s, weights %s" % (key, dt_s, out[key]["weights"]))
+        del psi, H, Hp, Hm, b, bp, bm, ws
+        torch.cuda.empty_cache()
+    out["speedup_fp32_mixed"] = round(out["fp64"]["seconds"] / out["fp32_mixed"]["seconds"], 3)
+    return out
+
+
 def batched_bench():
     """All 169 sectors of the N_s = 12 three-orbital impurity: one batched FP32-mixed
     Lanczos (graph-replayed steps) vs the same sectors solved one after another."""
@@ -263,6 +316,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ns18", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-green", action="store_true", help="skip the Green function at N_s=15")
     ap.add_argument("--e0-ns18", action="store_true", help=argparse.SUPPRESS)  # the default; kept for old scripts
     ap.add_argument("--no-e0-ns18", action="store_true", help="skip time-to-E0 at N_s=18 (about two minutes)")
     ap.add_argument("--pmc-pass", action="store_true",
@@ -368,6 +422,7 @@ def main():
             e0_18 = {"skipped": "device memory: %s" % str(e).splitlines()[0]}
             log("time-to-E0 N_s=18 skipped: out of device memory")
 
+    green = None if args.no_green else green_bench()
     batched = None if args.no_batched else batched_bench()
     cpu = None if args.no_cpu else cpu_baseline(2)
     if cpu:
@@ -393,6 +448,7 @@ def main():
         "time_to_e0_ns15_cgs2": e0_cgs2,
         "time_to_e0_ns18": e0_18,
         "batched_ns12": batched,
+        "green_ns15": green,
     }
     print(json.dumps(rec), flush=True)
 

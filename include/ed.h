@@ -236,6 +236,47 @@ ed_status ed_arnoldi_lowest(ed_ham_t h, int k, const ed_lanczos_opts *opts, cons
                             void *ws, size_t ws_bytes, double *evals, void *evecs,
                             ed_info *info, void *stream);
 
+/* Tridiagonal Lanczos coefficients of the Krylov space of v0 (no restart):
+ * m steps with the reorthogonalisation of opts->reorth (opts->max_basis and
+ * keep are ignored).  alpha[0..m), beta[0..m) HOST outputs with beta[j] the
+ * coupling of steps j and j+1; *steps = k <= m (fewer when the Krylov space is
+ * exhausted; then beta[k-1] = 0); *v0_norm2 = ||v0||^2.  These are the
+ * continued-fraction coefficients of <v0|(z - H)^-1|v0>, the form in which the
+ * impurity Green function of Eq. 3 is evaluated.  ws: DEVICE workspace of at
+ * least ed_workspace_bytes(h, opts with max_basis = m, 1).  Synchronous.
+ * EINVAL: m outside [1, min(D, 1022)], NULL arguments, v0 zero. */
+ed_status ed_lanczos_tridiag(ed_ham_t h, const ed_lanczos_opts *opts, const void *v0, int m, void *ws,
+                             size_t ws_bytes, double *alpha, double *beta, int *steps, double *v0_norm2,
+                             void *stream);
+
+/* y = c+_{site,spin} x (dagger = 1) or c_{site,spin} x (dagger = 0): x is a
+ * DEVICE vector of sector src, y of sector dst, which must hold one electron
+ * more (dagger) or less of that spin and the same number of the other spin,
+ * with the same Ns and precision.  The fermion sign follows the mode order of
+ * the Conventions (all up modes first).  These are the matrix elements
+ * <mu|c+_sigma|nu> of Eq. 3.  Asynchronous on stream.  EINVAL: sectors that do
+ * not match, site outside [0, Ns), NULL or aliasing vectors. */
+ed_status ed_apply_ladder(ed_ham_t src, ed_ham_t dst, int spin, int site, int dagger, const void *x, void *y,
+                          void *stream);
+
+/* Continued fraction on the host, ACCUMULATED into g: g(z) += weight * norm2 /
+ * (z - s(alpha_0 - e0) - beta_0^2 / (z - s(alpha_1 - e0) - ...)) over k levels,
+ * for nz complex z (z_re, z_im HOST arrays), s = +1 for the particle part
+ * <phi|(z - (H - e0))^-1|phi> and -1 for the hole part <phi|(z + (H - e0))^-1|phi>.
+ * g_re, g_im: HOST [nz], zeroed by the caller before the first term.  EINVAL:
+ * NULL arrays, k < 1, sign not +-1, non-finite weight or norm2. */
+ed_status ed_green_cf(const double *alpha, const double *beta, int k, double norm2, double e0, int sign,
+                      double weight, const double *z_re, const double *z_im, int nz, double *g_re, double *g_im);
+
+/* Boltzmann weights of Eq. 3 on the host: w[i] = exp(-beta (E[i] - E_min)) / Z
+ * for the n computed levels E[0..n) (any sectors), where levels whose share
+ * falls below cutoff get w = 0 and Z sums the kept ones, so the kept weights
+ * add to 1 and the Green function keeps its total spectral weight.  *kept:
+ * number of nonzero weights.  The temperature Green function is then
+ * sum_i w[i] G_i(z), each G_i the zero-temperature one of level i.  EINVAL:
+ * NULL arrays, n < 1, beta not in (0, inf), cutoff not in [0, 1), E non-finite. */
+ed_status ed_boltzmann_weights(const double *E, int n, double beta, double cutoff, double *w, int *kept);
+
 /* ------------------------------------------------------- sector batching ----
  * All sectors of one impurity problem at once (the paper's solver treats the
  * sectors of the block structure one after another): one restarted Lanczos per

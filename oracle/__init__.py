@@ -500,3 +500,101 @@ def terms_from_model(p: dict) -> List[Term]:
 
 def sector_for(p: dict, nup: int, ndn: int) -> Sector:
     return Sector(int(p["Ns"]), nup, ndn, terms_from_model(p))
+
+# ------------------------------------------------- Green function (Eq. 3) --
+
+def ladder_matrix(src: Sector, dst: Sector, spin: int, site: int, dagger: bool) -> np.ndarray:
+    """Dense matrix of c+_{site,spin} (dagger) or c_{site,spin} from sector src
+    to sector dst, literally: each basis state of src becomes a Fock word, the
+    one-operator string is applied with its Jordan-Wigner sign, and the result
+    is looked up in dst's basis.  Its entries are the <mu|c+_sigma|nu> of Eq. 3
+    in the occupation basis."""
+    ns = src.ns
+    mode = _mode(site, spin, ns)
+    mask = (1 << ns) - 1
+    L = np.zeros((dst.D, src.D))
+    for u, su in enumerate(src.up):
+        for d, sd in enumerate(src.dn):
+            r = apply_string(int(su) | (int(sd) << ns), [(mode, 1 if dagger else 0)])
+            if r is None:
+                continue
+            w2, sg = r
+            iu = int(np.searchsorted(dst.up, w2 & mask))
+            idn = int(np.searchsorted(dst.dn, w2 >> ns))
+            if iu >= dst.dup or dst.up[iu] != (w2 & mask) or idn >= dst.ddn or dst.dn[idn] != (w2 >> ns):
+                raise ValueError("ladder operator leaves the destination sector")
+            L[iu * dst.ddn + idn, u * src.ddn + d] += sg
+    return L
+
+
+def ladder(src: Sector, dst: Sector, spin: int, site: int, dagger: bool, x: np.ndarray) -> np.ndarray:
+    """c+_{site,spin} (dagger) or c_{site,spin} applied to a vector of sector src."""
+    return ladder_matrix(src, dst, spin, site, dagger) @ x
+
+
+def green_lehmann(p: dict, nup: int, ndn: int, spin: int, site: int, z) -> Tuple[np.ndarray, dict]:
+    """Eq. 3 at zero temperature, where only the ground state |0> of the sector
+    contributes (the Boltzmann weights of the other states vanish):
+        G(z) = sum_mu |<mu|c+|0>|^2 / (z - (E_mu - E_0))
+             + sum_nu |<nu|c|0>|^2 / (z + (E_nu - E_0)),
+    mu over the sector with one more electron of the given spin, nu over the
+    sector with one less, all by dense diagonalisation (small sectors only).
+    The paper prints the denominator as E_nu - E_mu - i w_n, the negative of
+    this standard Lehmann form (a sign convention); the form here is the one
+    whose U = 0 limit is the one-body resolvent (z - h)^-1."""
+    z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
+    s0 = sector_for(p, nup, ndn)
+    e, v = np.linalg.eigh(s0.dense())
+    if len(e) > 1 and e[1] - e[0] < 1e-8 * max(1.0, abs(e[0])):
+        raise ValueError("degenerate ground state: the zero-temperature limit is not unique")
+    e0, psi = e[0], v[:, 0]
+    g = np.zeros(len(z), dtype=np.complex128)
+    weights = {}
+    ns = s0.ns
+    n_sp = nup if spin == 0 else ndn
+    for part, dn_, sgn in (("particle", 1, 1.0), ("hole", -1, -1.0)):
+        n2 = n_sp + dn_
+        if n2 < 0 or n2 > ns:
+            weights[part] = 0.0
+            continue
+        s1 = sector_for(p, nup + (dn_ if spin == 0 else 0), ndn + (dn_ if spin == 1 else 0))
+        e1, v1 = np.linalg.eigh(s1.dense())
+        phi = ladder(s0, s1, spin, site, dn_ > 0, psi)
+        w = (v1.T @ phi) ** 2
+        weights[part] = float(np.sum(w))
+        g += np.sum(w[None, :] / (z[:, None] - sgn * (e1[None, :] - e0)), axis=1)
+    return g, {"E0": float(e0), "weights": weights}
+
+
+def green_thermal(p: dict, spin: int, site: int, beta: float, z) -> Tuple[np.ndarray, dict]:
+    """Eq. 3 at inverse temperature beta, as the double sum over all eigenpairs
+    of the whole Fock space (every (N_up, N_dn) sector, dense diagonalisation):
+        G(z) = (1/Z) sum_{nu, mu} |<mu|c+|nu>|^2 (e^{-beta E_nu} + e^{-beta E_mu})
+                                  / (z - (E_mu - E_nu)),
+    Z = sum_mu e^{-beta E_mu}, mu running over the sector with one more
+    electron of the given spin than nu's.  The denominator's sign is the
+    standard one (the reading taken for green_lehmann); energies are measured
+    from the lowest level so that the exponentials cannot overflow."""
+    z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
+    ns = int(p["Ns"])
+    eig = {}
+    for nu in range(ns + 1):
+        for nd in range(ns + 1):
+            sec = sector_for(p, nu, nd)
+            e, v = np.linalg.eigh(sec.dense())
+            eig[(nu, nd)] = (sec, e, v)
+    emin = min(float(e.min()) for _, e, _ in eig.values())
+    Z = sum(float(np.sum(np.exp(-beta * (e - emin)))) for _, e, _ in eig.values())
+    g = np.zeros(len(z), dtype=np.complex128)
+    for (nu, nd), (s0, e0, v0) in eig.items():
+        tgt = (nu + 1, nd) if spin == 0 else (nu, nd + 1)
+        if tgt not in eig:
+            continue
+        s1, e1, v1 = eig[tgt]
+        M = v1.T @ ladder_matrix(s0, s1, spin, site, True) @ v0      # M[mu, nu] = <mu|c+|nu>
+        fac = np.exp(-beta * (e0[None, :] - emin)) + np.exp(-beta * (e1[:, None] - emin))
+        num = (M ** 2 * fac).ravel()
+        den = (e1[:, None] - e0[None, :]).ravel()
+        keep = num != 0.0
+        g += np.sum(num[keep][None, :] / (z[:, None] - den[keep][None, :]), axis=1)
+    return g / Z, {"Z": Z, "Emin": emin}

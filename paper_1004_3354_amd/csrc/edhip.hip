@@ -6,3 +6,4 @@
 #include "fill.hip"
 #include "lanczos.hip"
 #include "batched.hip"
+#include "green.hip"

@@ -781,8 +781,63 @@ struct Solver {
         return true;
     }
 
+    // m Lanczos steps from v0 with no restart (the continued-fraction
+    // coefficients of a resolvent): alpha_h[0..k), beta_h[0..k) on the host,
+    // k <= m steps (fewer when the Krylov space is exhausted, beta_h[k-1] = 0),
+    // and ||v0||^2 in *v0n2.  Ground-state style storage: locked vectors none.
+    int tridiag(const void *v0, int m, double *alpha_h, double *beta_h, double *v0n2) {
+        ED_HIP(hipMemcpyAsync(w.slots[0], v0, (size_t)h->D * w.elem, hipMemcpyDeviceToDevice, s));
+        std::vector<void *> kr(w.slots.begin(), w.slots.end());
+        upload_pointers(kr);
+        *v0n2 = norm2_sync(0, kr[0]);
+        prepare_start(kr[0]);
+        k_zero<<<1, 256, 0, s>>>(w.alpha, m + 2);
+        k_zero<<<1, 256, 0, s>>>(w.beta, m + 2);
+        ED_LAUNCH_CHECK();
+        for (int j = 0; j < m; ++j) {
+            void *Y = kr[j + 1];
+            apply_launch(h, kr[j], Y, s);
+            const int nv = j + 1;
+            if (o.reorth == 3) {
+                dots_gram(nv, Y, kr[j], w.alpha + j);
+                update(0, nv, Y, w.partials, w.sig2 + j);
+            } else {
+                int vb = 0, nvec = nv;
+                if (o.reorth == 0 && j >= 2) {
+                    vb = j - 1;
+                    nvec = 2;
+                }
+                const int passes = o.reorth >= 2 ? 2 : 1;
+                for (int ps = 0; ps < passes; ++ps) {
+                    const bool last_pass = ps == passes - 1;
+                    dots(vb, nvec, Y, w.alpha + j, j - vb);
+                    update(vb, nvec, Y, last_pass ? w.partials : nullptr, last_pass ? w.sig2 + j : nullptr);
+                }
+            }
+            k_finalize_norm<<<1, 256, 0, s>>>(w.partials, w.nblk, w.sig2, w.beta, j, j);
+            ED_LAUNCH_CHECK();
+        }
+        ED_HIP(hipMemcpyAsync(alpha_h, w.alpha, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+        ED_HIP(hipMemcpyAsync(beta_h, w.beta, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+        ED_HIP(hipStreamSynchronize(s));
+        double scale = 1.0;
+        for (int j = 0; j < m; ++j) scale = std::max(scale, std::fabs(alpha_h[j]));
+        for (int j = 0; j < m; ++j) {
+            if (!std::isfinite(alpha_h[j]) || !std::isfinite(beta_h[j]))
+                fail(ED_EDEVICE, "non-finite Lanczos coefficients at step %d", j);
+            if (!(std::fabs(beta_h[j]) > 64.0 * 2.220446049250313e-16 * scale)) {
+                beta_h[j] = 0.0;
+                return j + 1;
+            }
+        }
+        return m;
+    }
+
     ed_status run(const void *v0, void *out, double *E, ed_info *info, int64_t fresh = -1) {
-        const int m = w.m;
+        // cycle length: at most the dimension of the space left after deflation;
+        // a cycle that spans all of it has exact Ritz values (up to rounding)
+        const int m = (int)std::min<int64_t>(w.m, h->D - nlock);
+        const bool spans = (int64_t)m == h->D - nlock && o.reorth >= 2;
         ed_info inf{};
         if (fresh >= 0) {
             k_fill<<<grid_for(h->D, 256, 1 << 16), 256, 0, s>>>(w.slots[0], h->D, (uint64_t)fresh, 1,
@@ -850,7 +905,7 @@ struct Solver {
                 const bool brk = std::fabs(tv[2]) <= 64.0 * eps * scale;
                 if (!std::isfinite(theta) || !std::isfinite(resid))
                     fail(ED_EDEVICE, "non-finite Lanczos coefficients (alpha/beta) at step %d", total);
-                if (resid <= o.tol * scale || brk) {
+                if (resid <= o.tol * scale || brk || (full && spans)) {
                     converged = true;
                     cycle_done = true;
                     break;
@@ -950,8 +1005,6 @@ extern "C" ed_status ed_workspace_bytes(ed_ham_t h, const ed_lanczos_opts *opts,
         if (k > 200) fail(ED_EINVAL, "ed_workspace_bytes: k=%d above 200", k);
         ed_lanczos_opts o = effective(opts, h->D);
         if (o.max_basis > kMaxVec - 2 - k) o.max_basis = kMaxVec - 2 - k;
-        const int64_t room = h->D - (k - 1);
-        if ((int64_t)o.max_basis > room) o.max_basis = (int)std::max<int64_t>(room, 1);
         *bytes = ws_needed(h, o, k, true);
     });
 }
@@ -968,11 +1021,9 @@ static ed_status solve(ed_ham_t h, int k, const ed_lanczos_opts *opts, const voi
         sv.h = h;
         sv.s = (hipStream_t)stream;
         sv.o = effective(opts, h->D);
-        // a basis of m vectors in a deflated space of dimension D - (k-1)
+        // eigenpair e runs cycles of at most D - e steps (the deflated space)
         if (k > 200) fail(ED_EINVAL, "k=%d above 200", k);
         if (sv.o.max_basis > kMaxVec - 2 - k) sv.o.max_basis = kMaxVec - 2 - k;
-        const int64_t room = h->D - (k - 1);
-        if ((int64_t)sv.o.max_basis > room) sv.o.max_basis = (int)std::max<int64_t>(room, 1);
         const bool locked_in_ws = (evecs == nullptr);
         const size_t need = ws_needed(h, sv.o, k, locked_in_ws);
         if (ws_bytes < need) fail(ED_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
@@ -1012,6 +1063,28 @@ static ed_status solve(ed_ham_t h, int k, const ed_lanczos_opts *opts, const voi
 extern "C" ed_status ed_lanczos_ground(ed_ham_t h, const ed_lanczos_opts *opts, const void *v0, void *ws,
                                        size_t ws_bytes, double *E0, void *psi0, ed_info *info, void *stream) {
     return solve(h, 1, opts, v0, ws, ws_bytes, E0, psi0, info, stream);
+}
+
+extern "C" ed_status ed_lanczos_tridiag(ed_ham_t h, const ed_lanczos_opts *opts, const void *v0, int m, void *ws,
+                                        size_t ws_bytes, double *alpha, double *beta, int *steps, double *v0_norm2,
+                                        void *stream) {
+    return guard([&] {
+        if (!h) fail(ED_EINVAL, "NULL handle");
+        if (!v0 || !ws || !alpha || !beta || !steps || !v0_norm2) fail(ED_EINVAL, "NULL argument");
+        if (m < 1 || (int64_t)m > h->D || m > kMaxVec - 2)
+            fail(ED_EINVAL, "m=%d outside [1, min(D=%lld, %d)]", m, (long long)h->D, kMaxVec - 2);
+        DeviceGuard g(h->device);
+        Solver sv;
+        sv.h = h;
+        sv.s = (hipStream_t)stream;
+        sv.o = effective(opts, h->D);
+        sv.o.max_basis = m;
+        sv.o.keep = 0;
+        const size_t need = ws_needed(h, sv.o, 1, true);
+        if (ws_bytes < need) fail(ED_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+        layout(sv.w, (char *)ws, h->D, h->prec == ED_FP64 ? 8 : 4, m, 1, true);
+        *steps = sv.tridiag(v0, m, alpha, beta, v0_norm2);
+    });
 }
 
 extern "C" ed_status ed_arnoldi_lowest(ed_ham_t h, int k, const ed_lanczos_opts *opts, const void *v0, void *ws,

@@ -96,6 +96,13 @@ _sig("ed_lanczos_ground", ctypes.c_int, [_p, ctypes.POINTER(ed_lanczos_opts), _p
                                          ctypes.POINTER(ctypes.c_double), _p, ctypes.POINTER(ed_info), _p])
 _sig("ed_arnoldi_lowest", ctypes.c_int, [_p, ctypes.c_int, ctypes.POINTER(ed_lanczos_opts), _p, _p,
                                          ctypes.c_size_t, _p, _p, _p, _p])
+_sig("ed_lanczos_tridiag", ctypes.c_int, [_p, ctypes.POINTER(ed_lanczos_opts), _p, ctypes.c_int, _p, ctypes.c_size_t,
+                                          _p, _p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), _p])
+_sig("ed_apply_ladder", ctypes.c_int, [_p, _p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _p, _p, _p])
+_sig("ed_green_cf", ctypes.c_int, [_p, _p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_double, _p, _p, ctypes.c_int, _p, _p])
+_sig("ed_boltzmann_weights", ctypes.c_int, [_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, _p,
+                                            ctypes.POINTER(ctypes.c_int)])
 if hasattr(_lib, "ed_lanczos_ground_batched"):
     _sig("ed_batched_workspace_bytes", ctypes.c_int, [ctypes.c_int, _p, ctypes.POINTER(ed_lanczos_opts),
                                                       ctypes.POINTER(ctypes.c_size_t)])
@@ -264,6 +271,24 @@ class Hamiltonian:
         _check(st, (ED_OK, ED_ENOCONV) if allow_noconv else (ED_OK,))
         return ev, [i.as_dict() for i in infos]
 
+    def lanczos_tridiag(self, v0, m: int, opts=None, ws=None, stream=None):
+        """(alpha, beta, ||v0||^2): k <= m tridiagonal Lanczos coefficients from v0."""
+        import torch
+        o = options() if opts is None else opts
+        o = ed_lanczos_opts.from_buffer_copy(o)
+        o.max_basis = m
+        nb = self.workspace_bytes(o, 1)
+        if ws is None:
+            ws = torch.empty(nb, dtype=torch.uint8, device=v0.device)
+        a = np.zeros(m, dtype=np.float64)
+        b = np.zeros(m, dtype=np.float64)
+        k = ctypes.c_int()
+        n2 = ctypes.c_double()
+        _check(_lib.ed_lanczos_tridiag(self._h, ctypes.byref(o), _dev_ptr(v0), m, _dev_ptr(ws), ws.numel(),
+                                       a.ctypes.data_as(_p), b.ctypes.data_as(_p), ctypes.byref(k), ctypes.byref(n2),
+                                       _stream(stream)))
+        return a[:k.value].copy(), b[:k.value].copy(), n2.value
+
     def close(self):
         if self._h:
             _lib.ed_ham_free(self._h)
@@ -314,3 +339,123 @@ def lanczos_ground_batched(hams: Sequence[Hamiltonian], opts=None, seed: int = 0
                                         E.ctypes.data_as(_p), ctypes.cast(infos, _p), _stream(stream))
     _check(st, (ED_OK, ED_ENOCONV) if allow_noconv else (ED_OK,))
     return E, [i.as_dict() for i in infos]
+
+
+def apply_ladder(src: "Hamiltonian", dst: "Hamiltonian", spin: int, site: int, dagger: bool, x, y, stream=None):
+    """y = c+_{site,spin} x (dagger) or c_{site,spin} x, from sector src to sector dst."""
+    _check(_lib.ed_apply_ladder(src._h, dst._h, int(spin), int(site), 1 if dagger else 0, _dev_ptr(x), _dev_ptr(y),
+                                _stream(stream)))
+
+
+def green_cf(alpha, beta, norm2: float, e0: float, sign: int, z, weight: float = 1.0, g=None):
+    """weight * norm2 / (z - sign (alpha_0 - e0) - beta_0^2 / (...)) at complex z,
+    added to g when given (complex128 array of len(z)), else returned."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
+    zr, zi = np.ascontiguousarray(z.real), np.ascontiguousarray(z.imag)
+    gr = np.ascontiguousarray(g.real) if g is not None else np.zeros(len(z))
+    gi = np.ascontiguousarray(g.imag) if g is not None else np.zeros(len(z))
+    _check(_lib.ed_green_cf(a.ctypes.data_as(_p), b.ctypes.data_as(_p), len(a), float(norm2), float(e0), int(sign),
+                            float(weight), zr.ctypes.data_as(_p), zi.ctypes.data_as(_p), len(z), gr.ctypes.data_as(_p),
+                            gi.ctypes.data_as(_p)))
+    out = gr + 1j * gi
+    if g is not None:
+        g[:] = out
+    return out
+
+
+def boltzmann_weights(E, beta: float, cutoff: float = 0.0):
+    """(w, kept): normalised Boltzmann weights of the levels E, levels whose share
+    is below cutoff dropped (w = 0) and the rest renormalised."""
+    e = np.ascontiguousarray(E, dtype=np.float64)
+    w = np.zeros(len(e))
+    kept = ctypes.c_int()
+    _check(_lib.ed_boltzmann_weights(e.ctypes.data_as(_p), len(e), float(beta), float(cutoff), w.ctypes.data_as(_p),
+                                     ctypes.byref(kept)))
+    return w, kept.value
+
+
+def green_function(H0: "Hamiltonian", e0: float, psi0, Hp: "Hamiltonian", Hm: "Hamiltonian", spin: int, site: int,
+                   z, m: int = 200, opts=None, weight: float = 1.0, g=None, ws=None):
+    """Impurity Green function of Eq. 3 for one eigenstate psi0 (energy e0) of
+    sector H0: G(z) = <psi0|c (z - (H - e0))^-1 c+|psi0> + <psi0|c+ (z + (H - e0))^-1 c|psi0>,
+    with c = c_{site,spin}.  Hp / Hm: the sectors with one electron of that spin
+    more / less (None where the sector does not exist).  weight * G is added to
+    g when given.  ws: optional DEVICE workspace for the Lanczos runs, large
+    enough for both neighbouring sectors.  Returns (G or g, details)."""
+    import torch
+    z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
+    if g is None:
+        g = np.zeros(len(z), dtype=np.complex128)
+    info = {}
+    for part, Hx, dag, sgn in (("particle", Hp, True, 1), ("hole", Hm, False, -1)):
+        if Hx is None:
+            continue
+        phi = torch.empty(Hx.D, dtype=psi0.dtype, device=psi0.device)
+        apply_ladder(H0, Hx, spin, site, dag, psi0, phi)
+        try:
+            a, b, n2 = Hx.lanczos_tridiag(phi, min(m, Hx.D), opts, ws=ws)
+        except EDError as err:  # c+ or c annihilates psi0 (zero start vector)
+            if err.status != ED_EINVAL or "zero" not in str(err):
+                raise
+            info[part] = {"weight": 0.0, "steps": 0}
+            continue
+        finally:
+            del phi
+        green_cf(a, b, n2, e0, sgn, z, weight=weight, g=g)
+        info[part] = {"weight": n2, "steps": len(a)}
+    return g, info
+
+
+def green_thermal(params: Dict, ns: int, sectors: Sequence[Tuple[int, int]], spin: int, site: int, beta: float, z,
+                  k: int = 20, cutoff: float = 1e-5, m: int = 200, precision: int = ED_FP64, opts=None,
+                  device: int = 0, seed: int = 1):
+    """Temperature Green function of Eq. 3: the k lowest levels of each sector in
+    `sectors` (ed_arnoldi_lowest), Boltzmann weights over all of them with the
+    cut `cutoff` (ed_boltzmann_weights), then each kept level's particle and hole
+    continued fractions (green_function) added with its weight.  The sectors
+    must hold every level with a weight above the cut; details["edge"] lists
+    the sectors whose k-th level still carries a weight at or above the cut
+    (more levels needed there).  Returns (G(z), details)."""
+    import torch
+    dev = torch.device("cuda", device)
+    dt = torch.float64 if precision == ED_FP64 else torch.float32
+    z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
+    hams = {}
+
+    def ham(sec):
+        if sec not in hams:
+            nu, nd = sec
+            if min(nu, nd) < 0 or max(nu, nd) > ns:
+                hams[sec] = None
+            else:
+                hams[sec] = Hamiltonian(params, Basis(ns, nu, nd), precision)
+        return hams[sec]
+
+    levels = []   # (sector, index, energy)
+    vecs = {}
+    for sec in sectors:
+        H = ham(tuple(sec))
+        kk = min(k, H.D)
+        v0 = torch.empty(H.D, dtype=dt, device=dev)
+        fill_random(v0, seed, 1)
+        ev = torch.empty(kk * H.D, dtype=dt, device=dev)
+        E, _ = H.lowest(kk, v0, opts, evecs=ev)
+        vecs[tuple(sec)] = ev
+        levels += [(tuple(sec), i, float(e)) for i, e in enumerate(E)]
+    w, kept = boltzmann_weights([l[2] for l in levels], beta, cutoff)
+    g = np.zeros(len(z), dtype=np.complex128)
+    # a sector whose highest computed level survives the cut may hold more such levels
+    edge = sorted({sec for (sec, i, e), wi in zip(levels, w) if wi > 0.0 and i == k - 1 and k < ham(sec).D})
+    for (sec, i, e), wi in zip(levels, w):
+        if wi == 0.0:
+            continue
+        H0 = ham(sec)
+        psi = vecs[sec][i * H0.D:(i + 1) * H0.D]
+        nu, nd = sec
+        up = (nu + 1, nd) if spin == 0 else (nu, nd + 1)
+        dn = (nu - 1, nd) if spin == 0 else (nu, nd - 1)
+        green_function(H0, e, psi, ham(up), ham(dn), spin, site, z, m=m, opts=opts, weight=wi, g=g)
+    details = {"levels": [(sec, i, e, float(wi)) for (sec, i, e), wi in zip(levels, w)], "kept": kept, "edge": edge}
+    return g, details
