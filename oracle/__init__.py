@@ -121,7 +121,10 @@ def terms_generic(ns: int, eps, hop, w_ud, w_ss, xterms: Iterable = ()) -> List[
     sum_{i,s} eps[s,i] n_is + sum_{s, i!=j} hop[s,i,j] c+_is c_js
     + sum_{i,j} w_ud[i,j] n_i,up n_j,dn + sum_{s, i<j} w_ss[s,i,j] n_is n_js
     + sum over (type, m, m', c) of c * (spin-flip or pair-hopping string as written
-    in the multi-orbital Hamiltonian of Section 4)."""
+    in the multi-orbital Hamiltonian of Section 4)
+    + sum over (3, i, j, k, l, c) of c * c+_{i up} c+_{j dn} c_{l dn} c_{k up}, an
+    opposite-spin element U_ijkl of a full two-body U-matrix (Section 4's
+    closing remark on the other non-diagonal elements)."""
     eps = np.asarray(eps, dtype=np.float64).reshape(2, ns)
     hop = np.asarray(hop, dtype=np.float64).reshape(2, ns, ns)
     w_ud = np.asarray(w_ud, dtype=np.float64).reshape(ns, ns)
@@ -146,13 +149,19 @@ def terms_generic(ns: int, eps, hop, w_ud, w_ss, xterms: Iterable = ()) -> List[
                 if w_ss[s, i, j] != 0.0:
                     T.append((float(w_ss[s, i, j]),
                               _number(_mode(i, s, ns)) + _number(_mode(j, s, ns))))
-    for (typ, m, mp, c) in xterms:
-        T.append((float(c), _xstring(typ, m, mp, ns)))
+    for xt in xterms:
+        if xt[0] == UD_GENERAL:
+            _, i, j, k, l, c = xt
+            T.append((float(c), [(_up(i, ns), 1), (_dn(j, ns), 1), (_dn(l, ns), 0), (_up(k, ns), 0)]))
+        else:
+            typ, m, mp, c = xt
+            T.append((float(c), _xstring(typ, m, mp, ns)))
     return T
 
 
 SPIN_FLIP = 1
 PAIR_HOP = 2
+UD_GENERAL = 3
 
 
 def _xstring(typ: int, m: int, mp: int, ns: int) -> List[Tuple[int, int]]:

@@ -189,7 +189,9 @@ __global__ void k_move(const uint32_t *st, int64_t dim, int ns, int n, int src, 
          r += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t s = st[r];
         int32_t v = -1;
-        if (((s >> src) & 1u) && !((s >> dst) & 1u)) {
+        if (src == dst) {
+            if ((s >> src) & 1u) v = (int32_t)(r << 1);  // c+_i c_i = n_i: same state, no sign
+        } else if (((s >> src) & 1u) && !((s >> dst) & 1u)) {
             const uint32_t s2 = s ^ (1u << src) ^ (1u << dst);
             const int64_t t = rank_state(s2, ns, n);
             const int neg = __popc(s & between_mask(src, dst)) & 1;
@@ -482,13 +484,20 @@ static void build_cross(ed_ham_s *h, const ed_params *p) {
 // Four-fermion terms as products of one-spin moves (Section 4):
 //   d+_{m up} d_{m dn} d+_{m' dn} d_{m' up} = -(d+_{m up} d_{m' up})(d+_{m' dn} d_{m dn})
 //   d+_{m up} d+_{m dn} d_{m' up} d_{m' dn} = -(d+_{m up} d_{m' up})(d+_{m dn} d_{m' dn})
+//   c+_{i up} c+_{j dn} c_{l dn} c_{k up}   = +(c+_{i up} c_{k up})(c+_{j dn} c_{l dn})
 // (anticommuting the operators past each other), and an even down-spin pair
 // passes the up block without a sign.  So a term with coefficient c acting on
-// (u, d) gives (up: m' -> m, down: m -> m' or m' -> m) with element -c s_up s_dn.
+// (u, d) gives (up: m' -> m, down: m -> m' or m' -> m) with element -c s_up s_dn,
+// or (up: k -> i, down: l -> j) with element +c s_up s_dn; a move onto its own
+// site (k = i or l = j) is the number operator.
 static void build_xterms(ed_ham_s *h, const ed_params *p) {
     std::map<std::pair<int, int>, double> acc;  // (up move, dn move) -> amplitude
     for (int t = 0; t < p->n_x; ++t) {
         const ed_xterm &x = p->x[t];
+        if (x.type == ED_UD_GENERAL) {
+            acc[{move_index(h->sp[0], x.k, x.m), move_index(h->sp[1], x.l, x.mp)}] += x.coef;
+            continue;
+        }
         const int um = move_index(h->sp[0], x.mp, x.m);
         const int dm = (x.type == ED_SPIN_FLIP) ? move_index(h->sp[1], x.m, x.mp) : move_index(h->sp[1], x.mp, x.m);
         acc[{um, dm}] += -x.coef;
@@ -599,8 +608,16 @@ static void validate(const ed_params *p, int ns) {
         }
     }
     std::map<std::tuple<int, int, int>, double> sum;
+    std::map<std::tuple<int, int, int, int>, double> gsum;
     for (int t = 0; t < p->n_x; ++t) {
         const ed_xterm &x = p->x[t];
+        if (x.type == ED_UD_GENERAL) {
+            for (int q : {x.m, x.mp, x.k, x.l})
+                if (q < 0 || q >= ns) fail(ED_EINVAL, "ed_ham_create: general term index %d outside [0, Ns)", q);
+            if (!std::isfinite(x.coef)) fail(ED_EINVAL, "ed_ham_create: non-finite term coefficient");
+            gsum[std::make_tuple(x.m, x.mp, x.k, x.l)] += x.coef;
+            continue;
+        }
         if (x.type != ED_SPIN_FLIP && x.type != ED_PAIR_HOP) fail(ED_EINVAL, "ed_ham_create: bad term type %d", x.type);
         if (x.m < 0 || x.mp < 0 || x.m >= ns || x.mp >= ns || x.m == x.mp)
             fail(ED_EINVAL, "ed_ham_create: bad orbital pair (%d,%d)", x.m, x.mp);
@@ -613,6 +630,13 @@ static void validate(const ed_params *p, int ns) {
         if (other != kv.second)
             fail(ED_EINVAL, "ed_ham_create: four-fermion terms are not Hermitian (type %d, %d, %d)",
                  std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first));
+    }
+    for (auto &kv : gsum) {
+        int i, j, k, l;
+        std::tie(i, j, k, l) = kv.first;
+        auto it = gsum.find(std::make_tuple(k, l, i, j));
+        if ((it == gsum.end() ? 0.0 : it->second) != kv.second)
+            fail(ED_EINVAL, "ed_ham_create: general terms are not Hermitian at (%d, %d, %d, %d)", i, j, k, l);
     }
 }
 

@@ -39,7 +39,7 @@ class EDError(RuntimeError):
 
 class ed_xterm(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("m", ctypes.c_int32), ("mp", ctypes.c_int32),
-                ("coef", ctypes.c_double)]
+                ("coef", ctypes.c_double), ("k", ctypes.c_int32), ("l", ctypes.c_int32)]
 
 
 class ed_params(ctypes.Structure):
@@ -184,8 +184,12 @@ def make_params(p: Dict):
     arrs = [np.ascontiguousarray(np.asarray(p[k], dtype=np.float64)) for k in ("eps", "hop", "w_ud", "w_ss")]
     xt = p.get("xterms", [])
     xa = (ed_xterm * max(len(xt), 1))()
-    for i, (t, m, mp, c) in enumerate(xt):
-        xa[i] = ed_xterm(int(t), int(m), int(mp), float(c))
+    for i, x in enumerate(xt):
+        if len(x) == 6:      # (ED_UD_GENERAL, i, j, k, l, coef)
+            t, m, mp, k, l, c = x
+        else:                # (type, m, m', coef)
+            (t, m, mp, c), k, l = x, 0, 0
+        xa[i] = ed_xterm(int(t), int(m), int(mp), float(c), int(k), int(l))
     s = ed_params(ns, arrs[0].ctypes.data_as(_p), arrs[1].ctypes.data_as(_p), arrs[2].ctypes.data_as(_p),
                   arrs[3].ctypes.data_as(_p), len(xt), ctypes.cast(xa, _p) if xt else None)
     return s, (arrs, xa)
@@ -382,12 +386,18 @@ def green_function(H0: "Hamiltonian", e0: float, psi0, Hp: "Hamiltonian", Hm: "H
     sector H0: G(z) = <psi0|c (z - (H - e0))^-1 c+|psi0> + <psi0|c+ (z + (H - e0))^-1 c|psi0>,
     with c = c_{site,spin}.  Hp / Hm: the sectors with one electron of that spin
     more / less (None where the sector does not exist).  weight * G is added to
-    g when given.  ws: optional DEVICE workspace for the Lanczos runs, large
+    g when given.  opts: Lanczos options of the two runs; by default the plain
+    three-term recurrence (reorth = 0), which is the usual choice for continued
+    fractions: lost orthogonality duplicates converged poles but leaves the
+    moments the fraction matches intact, at a fraction of the cost of full
+    reorthogonalisation.  ws: optional DEVICE workspace for the Lanczos runs, large
     enough for both neighbouring sectors.  Returns (G or g, details)."""
     import torch
     z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
     if g is None:
         g = np.zeros(len(z), dtype=np.complex128)
+    if opts is None:
+        opts = options(reorth=0)
     info = {}
     for part, Hx, dag, sgn in (("particle", Hp, True, 1), ("hole", Hm, False, -1)):
         if Hx is None:
@@ -408,16 +418,75 @@ def green_function(H0: "Hamiltonian", e0: float, psi0, Hp: "Hamiltonian", Hm: "H
     return g, info
 
 
+def lowest_levels(hams: Sequence["Hamiltonian"], K: int, opts=None, seed: int = 1, kmax: int = 200, progress=None):
+    """The K lowest levels, counted with multiplicity, over the sectors `hams`
+    (the thermal set behind Eq. 3).  Ground energies of every sector come from
+    one batched run (ed_lanczos_ground_batched); then, while some sector's
+    highest computed level lies at or below the K-th lowest level found so
+    far, that sector's level count is doubled (ed_arnoldi_lowest), since only
+    such a sector can hold another of the K.  Returns (levels, vectors,
+    details): levels = [(E, sector index, level index)] ascending (the K
+    lowest, more where a multiplet straddles the K-th), vectors = {sector
+    index: DEVICE tensor [k, D]} for the sectors with a level in the list,
+    details = counts and the sectors capped at kmax.  progress: optional
+    callable taking one line of text after each round."""
+    import torch
+    n = len(hams)
+    E0, _ = lanczos_ground_batched(hams, opts, seed=seed)
+    energies = {s: [float(E0[s])] for s in range(n)}
+    vecs = {}
+    calls = 0
+
+    def solve(s, k):
+        nonlocal calls
+        H = hams[s]
+        dt = torch.float64 if H.precision == ED_FP64 else torch.float32
+        v0 = torch.empty(H.D, dtype=dt, device="cuda")
+        fill_random(v0, seed + s, 1)
+        ev = torch.empty((k, H.D), dtype=dt, device="cuda")
+        try:
+            E, _ = H.lowest(k, v0, opts, evecs=ev)
+        except EDError as err:
+            raise EDError(err.status, "sector %d (D=%d), k=%d: %s" % (s, H.D, k, err)) from None
+        energies[s] = [float(e) for e in E]   # discovery order (ascending up to rounding) = row order
+        vecs[s] = ev
+        calls += 1
+
+    def threshold():
+        allE = sorted(e for es in energies.values() for e in es)
+        return allE[K - 1] if len(allE) >= K else float("inf")
+
+    capped = set()
+    while True:
+        T = threshold()
+        grow = [s for s in range(n) if max(energies[s]) <= T and len(energies[s]) < min(hams[s].D, kmax)]
+        if not grow:
+            break
+        for s in grow:
+            solve(s, min(hams[s].D, kmax, 2 * len(energies[s])))
+            if len(energies[s]) == kmax and max(energies[s]) <= T:
+                capped.add(s)
+        if progress:
+            progress("lowest_levels: %d sectors grown below %.6g, %d lowest calls" % (len(grow), T, calls))
+    T = threshold()
+    levels = sorted((e, s, i) for s, es in energies.items() for i, e in enumerate(es) if e <= T)
+    for s in sorted({s for _, s, _ in levels} - set(vecs)):
+        solve(s, 1)                  # one-level sectors: ground energy known, vector not yet
+    return levels, {s: vecs[s] for s in {s for _, s, _ in levels}}, {"lowest_calls": calls,
+                                                                    "capped": sorted(capped), "threshold": T}
+
+
 def green_thermal(params: Dict, ns: int, sectors: Sequence[Tuple[int, int]], spin: int, site: int, beta: float, z,
                   k: int = 20, cutoff: float = 1e-5, m: int = 200, precision: int = ED_FP64, opts=None,
-                  device: int = 0, seed: int = 1):
+                  device: int = 0, seed: int = 1, K: Optional[int] = None):
     """Temperature Green function of Eq. 3: the k lowest levels of each sector in
-    `sectors` (ed_arnoldi_lowest), Boltzmann weights over all of them with the
-    cut `cutoff` (ed_boltzmann_weights), then each kept level's particle and hole
-    continued fractions (green_function) added with its weight.  The sectors
-    must hold every level with a weight above the cut; details["edge"] lists
-    the sectors whose k-th level still carries a weight at or above the cut
-    (more levels needed there).  Returns (G(z), details)."""
+    `sectors` (ed_arnoldi_lowest) or, with K, the K lowest levels over all of
+    them (lowest_levels); Boltzmann weights over those levels with the cut
+    `cutoff` (ed_boltzmann_weights), then each kept level's particle and hole
+    continued fractions (green_function) added with its weight.  The levels
+    must include every one with a weight above the cut; details["edge"] lists
+    the sectors whose highest computed level still carries a weight at or above
+    the cut (more levels needed there).  Returns (G(z), details)."""
     import torch
     dev = torch.device("cuda", device)
     dt = torch.float64 if precision == ED_FP64 else torch.float32
@@ -435,7 +504,12 @@ def green_thermal(params: Dict, ns: int, sectors: Sequence[Tuple[int, int]], spi
 
     levels = []   # (sector, index, energy)
     vecs = {}
-    for sec in sectors:
+    if K is not None:
+        secs = [tuple(sec) for sec in sectors]
+        lv, vv, ldet = lowest_levels([ham(sec) for sec in secs], K, opts, seed=seed)
+        levels = [(secs[s], i, e) for e, s, i in lv]
+        vecs = {secs[s]: v.reshape(-1) for s, v in vv.items()}
+    for sec in (sectors if K is None else []):
         H = ham(tuple(sec))
         kk = min(k, H.D)
         v0 = torch.empty(H.D, dtype=dt, device=dev)
@@ -447,7 +521,10 @@ def green_thermal(params: Dict, ns: int, sectors: Sequence[Tuple[int, int]], spi
     w, kept = boltzmann_weights([l[2] for l in levels], beta, cutoff)
     g = np.zeros(len(z), dtype=np.complex128)
     # a sector whose highest computed level survives the cut may hold more such levels
-    edge = sorted({sec for (sec, i, e), wi in zip(levels, w) if wi > 0.0 and i == k - 1 and k < ham(sec).D})
+    if K is None:
+        edge = sorted({sec for (sec, i, e), wi in zip(levels, w) if wi > 0.0 and i == k - 1 and k < ham(sec).D})
+    else:   # every sector's levels up to the K-th are in; weight left on the K-th itself
+        edge = [] if w[-1] == 0.0 or len(levels) < K else ["K-th level above the cut"]
     for (sec, i, e), wi in zip(levels, w):
         if wi == 0.0:
             continue

@@ -165,7 +165,7 @@ _LEHMANN = {}
     ("hub6_33_dn5", wl.hubbard(3, 2, 1.0, 4.0, periodic=False), (3, 3), 1, 5),
     ("aim8_44_up0", wl.aim(7, 2.0, -1.0, seed=7), (4, 4), 0, 0),
 ])
-@pytest.mark.parametrize("reorth", [2, 3])
+@pytest.mark.parametrize("reorth", [0, 2, 3])
 def test_green_function_vs_lehmann(name, phys, nn, spin, site, prec, reorth):
     z = np.concatenate([ZM, ZR])
     if name not in _LEHMANN:
@@ -297,3 +297,49 @@ def test_green_thermal_truncated_within_bound():
     bound = 2.0 * delta / np.min(ZM.imag) + 1e-9
     assert det["kept"] >= 2
     assert np.max(np.abs(g - ref)) <= bound, (np.max(np.abs(g - ref)), delta)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_lowest_levels_over_all_sectors(prec):
+    """The K lowest levels over all 49 sectors of an N_s = 6 three-orbital
+    impurity, with multiplicity, against the dense spectra of every sector."""
+    ed = gpu_ed()
+    from paper_1004_3354_amd import models
+    phys = wl.kanamori(3, 1, 2.3, 0.4, seed=3)
+    ns = int(phys["Ns"])
+    secs = _all_sectors(ns)
+    ref = sorted((e, s) for s, (u, d) in enumerate(secs) for e in np.linalg.eigvalsh(sector(phys, u, d).dense()))
+    hams = [build(phys, u, d, prec)[1] for (u, d) in secs]
+    K = 60
+    levels, vecs, det = ed.lowest_levels(hams, K, _thermal_opts(prec))
+    tol = 1e-10 if prec == 0 else 1e-6
+    assert len(levels) >= K and det["capped"] == []
+    got = np.array([e for e, _, _ in levels[:K]])
+    want = np.array([e for e, _ in ref[:K]])
+    assert np.max(np.abs(got - want)) <= tol * max(1.0, np.max(np.abs(want)))
+    # each level's vector is an eigenvector of its sector with that energy
+    for e, s, i in levels[:K]:
+        H = hams[s]
+        psi = vecs[s][i]
+        hp = torch.empty_like(psi)
+        H.apply(psi, hp)
+        r = (hp.double() - e * psi.double()).norm().item() / psi.double().norm().item()
+        assert r <= (1e-8 if prec == 0 else 1e-4), (secs[s], i, r)
+
+
+def test_green_thermal_lowest_levels_vs_eq3():
+    """The thermal Green function from the K lowest levels over all sectors
+    against the full Eq. 3 sum, within the bound set by the levels left out."""
+    ed = gpu_ed()
+    from paper_1004_3354_amd import models
+    phys = wl.kanamori(3, 1, 2.3, 0.4, seed=3)
+    ns = int(phys["Ns"])
+    beta = 4.0
+    ref, rinfo = orc.green_thermal(phys, 1, 2, beta, ZM)
+    g, det = ed.green_thermal(models.params_from_model(phys), ns, _all_sectors(ns), 1, 2, beta, ZM, K=40,
+                              cutoff=0.0, m=500, precision=0, opts=_thermal_opts(0))
+    kept = [e for (_, _, e, w) in det["levels"] if w > 0.0]
+    share = sum(np.exp(-beta * (e - rinfo["Emin"])) for e in kept) / rinfo["Z"]
+    delta = max(0.0, 1.0 - share)
+    assert len(kept) >= 40
+    assert np.max(np.abs(g - ref)) <= 2.0 * delta / np.min(ZM.imag) + 1e-9, (np.max(np.abs(g - ref)), delta)
