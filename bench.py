@@ -251,7 +251,8 @@ def thermal_bench(K=300, beta=58.0, cutoff=1e-5, m=100):
     hams = [ed.Hamiltonian(p, ed.Basis(ns, u, d), ed.ED_FP64) for (u, d) in sectors]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    levels, vecs, det = ed.lowest_levels(hams, K, ed.options(tol=1e-8, max_iter=6000), progress=log)
+    opts = ed.options(tol=1e-8, max_iter=20000, max_basis=48, keep=16)
+    levels, vecs, det = ed.lowest_levels(hams, K, opts, progress=log)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     w, kept = ed.boltzmann_weights([e for e, _, _ in levels], beta, cutoff)

@@ -200,8 +200,9 @@ typedef struct {
     int32_t keep;         /* restart: 0 = from the current Ritz vector alone (default);
                              k >= 1 = implicit restart keeping k vectors (the unwanted
                              Ritz values applied as exact shifts to the tridiagonal
-                             matrix, which stays tridiagonal); ground state only,
-                             k <= 16, k < max_basis <= 256                           */
+                             matrix, which stays tridiagonal), for the ground state
+                             and for each eigenpair of ed_arnoldi_lowest on its
+                             deflated space; k <= 16, k < max_basis <= 256           */
 } ed_lanczos_opts;
 
 typedef struct {
@@ -242,6 +243,19 @@ ed_status ed_lanczos_ground(ed_ham_t h, const ed_lanczos_opts *opts, const void 
 ed_status ed_arnoldi_lowest(ed_ham_t h, int k, const ed_lanczos_opts *opts, const void *v0,
                             void *ws, size_t ws_bytes, double *evals, void *evecs,
                             ed_info *info, void *stream);
+
+/* ed_arnoldi_lowest continued: evecs[0..k0) (DEVICE [k][D], required) already
+ * hold converged orthonormal eigenvectors of h, e.g. from an earlier call, and
+ * evals[0..k0) their values; eigenpairs k0..k-1 are computed on the space
+ * orthogonal to them (the same explicit deflation), so a caller can raise k
+ * without recomputing the levels it has.  Eigenpairs e >= 1 start from the
+ * counter-based random stream, so v0 only has to be a valid vector.
+ * info[k0..k) is filled.  With k0 = 0 this is ed_arnoldi_lowest.  EINVAL: k0
+ * outside [0, k), evecs NULL with k0 > 0, a given vector of zero norm; the
+ * rest as ed_arnoldi_lowest. */
+ed_status ed_arnoldi_lowest_more(ed_ham_t h, int k0, int k, const ed_lanczos_opts *opts, const void *v0,
+                                 void *ws, size_t ws_bytes, double *evals, void *evecs, ed_info *info,
+                                 void *stream);
 
 /* Tridiagonal Lanczos coefficients of the Krylov space of v0 (no restart):
  * m steps with the reorthogonalisation of opts->reorth (opts->max_basis and

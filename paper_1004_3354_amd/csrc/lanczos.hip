@@ -713,7 +713,8 @@ struct Solver {
         std::vector<double> al((size_t)m), be((size_t)m), sg((size_t)m + 1);
         ED_HIP(hipMemcpyAsync(al.data(), w.alpha, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
         ED_HIP(hipMemcpyAsync(be.data(), w.beta, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
-        ED_HIP(hipMemcpyAsync(sg.data(), w.sig2, (size_t)(m + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        // Krylov entries of the pointer and sigma tables follow the nlock locked ones
+        ED_HIP(hipMemcpyAsync(sg.data(), w.sig2 + nlock, (size_t)(m + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         ED_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < m; ++i)
             if (!std::isfinite(al[i]) || !std::isfinite(be[i]) || !(sg[i] > 0.0)) return false;
@@ -747,11 +748,11 @@ struct Solver {
         C[(size_t)m * nout + k] = be[m - 1] * std::sqrt(sg[m]) * Q[(size_t)(m - 1) * m + (k - 1)];
         ED_HIP(hipMemcpyAsync(w.rcoef, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, s));
         if (h->prec == ED_FP64)
-            k_restart_combine<double><<<w.nblk, kRedBS, 0, s>>>((const double *const *)w.vp, w.rcoef, nin, nout, h->D,
-                                                               w.partials);
+            k_restart_combine<double><<<w.nblk, kRedBS, 0, s>>>((const double *const *)w.vp + nlock, w.rcoef, nin, nout,
+                                                               h->D, w.partials);
         else
-            k_restart_combine<float><<<w.nblk, kRedBS, 0, s>>>((const float *const *)w.vp, w.rcoef, nin, nout, h->D,
-                                                              w.partials);
+            k_restart_combine<float><<<w.nblk, kRedBS, 0, s>>>((const float *const *)w.vp + nlock, w.rcoef, nin, nout,
+                                                              h->D, w.partials);
         ED_LAUNCH_CHECK();
         k_finalize_dots<<<1, 256, 0, s>>>(w.partials, 1, w.nblk, nullptr, w.raw, nullptr, nullptr, 0);
         ED_LAUNCH_CHECK();
@@ -771,8 +772,8 @@ struct Solver {
         ns[k] = *breakdown ? 0.0 : 1.0 / n2;
         ED_HIP(hipMemcpyAsync(w.alpha, na.data(), na.size() * sizeof(double), hipMemcpyHostToDevice, s));
         ED_HIP(hipMemcpyAsync(w.beta, nbv.data(), nbv.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        ED_HIP(hipMemcpyAsync(w.sig2, ns.data(), ns.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        if (o.reorth == 3) {
+        ED_HIP(hipMemcpyAsync(w.sig2 + nlock, ns.data(), ns.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        if (o.reorth == 3 && nlock == 0) {
             std::vector<double> G((size_t)(m + 1) * (m + 1), 0.0);
             for (int i = 0; i < k; ++i) G[(size_t)i * (m + 1) + i] = 1.0;
             ED_HIP(hipMemcpyAsync(w.gram, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice, s));
@@ -925,7 +926,7 @@ struct Solver {
                 break;
             }
             bool brk_ir = false;
-            if (o.keep > 0 && nlock == 0 && jlast == m && implicit_restart(m, o.keep, &brk_ir)) {
+            if (o.keep > 0 && o.keep < m && jlast == m && implicit_restart(m, o.keep, &brk_ir)) {
                 ++inf.restarts;
                 jstart = o.keep;
                 if (brk_ir) {
@@ -1009,13 +1010,18 @@ extern "C" ed_status ed_workspace_bytes(ed_ham_t h, const ed_lanczos_opts *opts,
     });
 }
 
+// k0 > 0: evecs[0..k0) already hold converged, orthonormal eigenvectors (and
+// evals[0..k0) their values); they are locked as they are and only the
+// eigenpairs k0..k-1 are computed.
 static ed_status solve(ed_ham_t h, int k, const ed_lanczos_opts *opts, const void *v0, void *ws, size_t ws_bytes,
-                       double *evals, void *evecs, ed_info *info, void *stream) {
+                       double *evals, void *evecs, ed_info *info, void *stream, int k0 = 0) {
     ed_status result = ED_OK;
     ed_status st = guard([&] {
         if (!h) fail(ED_EINVAL, "NULL handle");
         if (!v0 || !ws || !evals) fail(ED_EINVAL, "NULL start vector, workspace or output");
         if (k < 1 || (int64_t)k > h->D) fail(ED_EINVAL, "k=%d outside [1, D=%lld]", k, (long long)h->D);
+        if (k0 < 0 || k0 >= k || (k0 > 0 && !evecs))
+            fail(ED_EINVAL, "k0=%d outside [0, k=%d) or no eigenvector array to continue from", k0, k);
         DeviceGuard g(h->device);
         Solver sv;
         sv.h = h;
@@ -1031,6 +1037,17 @@ static ed_status solve(ed_ham_t h, int k, const ed_lanczos_opts *opts, const voi
         if (!locked_in_ws)
             for (int i = 0; i < k; ++i) sv.w.locked[i] = (char *)evecs + (size_t)i * h->D * sv.w.elem;
         for (int e = 0; e < k; ++e) {
+            if (e < k0) {  // given: lock it as it is
+                sv.nlock = e;
+                const void *p = sv.w.locked[e];
+                ED_HIP(hipMemcpyAsync(sv.w.vp + e, &p, sizeof(void *), hipMemcpyHostToDevice, sv.s));
+                ED_HIP(hipStreamSynchronize(sv.s));
+                const double n2 = sv.norm2_sync(e, p);
+                if (!(n2 > 0.0)) fail(ED_EINVAL, "given eigenvector %d has zero norm", e);
+                sv.lock_sig2.push_back(1.0 / n2);
+                sv.nlock = e + 1;
+                continue;
+            }
             double E = 0.0;
             ed_info inf{};
             // A Krylov space built from one start vector holds a single vector per
@@ -1055,6 +1072,7 @@ static ed_status solve(ed_ham_t h, int k, const ed_lanczos_opts *opts, const voi
         // already ascending up to rounding; report them sorted with vectors kept
         // in discovery order only if no vectors were requested
         if (!evecs) std::sort(evals, evals + k);
+        (void)k0;
     });
     if (st != ED_OK) return st;
     return result;
@@ -1090,4 +1108,10 @@ extern "C" ed_status ed_lanczos_tridiag(ed_ham_t h, const ed_lanczos_opts *opts,
 extern "C" ed_status ed_arnoldi_lowest(ed_ham_t h, int k, const ed_lanczos_opts *opts, const void *v0, void *ws,
                                        size_t ws_bytes, double *evals, void *evecs, ed_info *info, void *stream) {
     return solve(h, k, opts, v0, ws, ws_bytes, evals, evecs, info, stream);
+}
+
+extern "C" ed_status ed_arnoldi_lowest_more(ed_ham_t h, int k0, int k, const ed_lanczos_opts *opts, const void *v0,
+                                            void *ws, size_t ws_bytes, double *evals, void *evecs, ed_info *info,
+                                            void *stream) {
+    return solve(h, k, opts, v0, ws, ws_bytes, evals, evecs, info, stream, k0);
 }

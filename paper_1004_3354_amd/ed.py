@@ -96,6 +96,8 @@ _sig("ed_lanczos_ground", ctypes.c_int, [_p, ctypes.POINTER(ed_lanczos_opts), _p
                                          ctypes.POINTER(ctypes.c_double), _p, ctypes.POINTER(ed_info), _p])
 _sig("ed_arnoldi_lowest", ctypes.c_int, [_p, ctypes.c_int, ctypes.POINTER(ed_lanczos_opts), _p, _p,
                                          ctypes.c_size_t, _p, _p, _p, _p])
+_sig("ed_arnoldi_lowest_more", ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ed_lanczos_opts), _p,
+                                              _p, ctypes.c_size_t, _p, _p, _p, _p])
 _sig("ed_lanczos_tridiag", ctypes.c_int, [_p, ctypes.POINTER(ed_lanczos_opts), _p, ctypes.c_int, _p, ctypes.c_size_t,
                                           _p, _p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), _p])
 _sig("ed_apply_ladder", ctypes.c_int, [_p, _p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _p, _p, _p])
@@ -275,6 +277,23 @@ class Hamiltonian:
         _check(st, (ED_OK, ED_ENOCONV) if allow_noconv else (ED_OK,))
         return ev, [i.as_dict() for i in infos]
 
+    def lowest_more(self, k0: int, k: int, evals0, v0, evecs, opts=None, ws=None, stream=None, allow_noconv=False):
+        """Levels k0..k-1 on top of the k0 converged ones in evecs[:k0] (values
+        evals0); evecs: DEVICE [k, D].  Returns (evals[k], infos[k0..k))."""
+        import torch
+        o = opts if opts is not None else options()
+        nb = self.workspace_bytes(o, k)
+        if ws is None:
+            ws = torch.empty(nb, dtype=torch.uint8, device=v0.device)
+        ev = np.zeros(k, dtype=np.float64)
+        ev[:k0] = np.asarray(evals0, dtype=np.float64)[:k0]
+        infos = (ed_info * k)()
+        st = _lib.ed_arnoldi_lowest_more(self._h, k0, k, ctypes.byref(o), _dev_ptr(v0), _dev_ptr(ws), ws.numel(),
+                                         ev.ctypes.data_as(_p), _dev_ptr(evecs), ctypes.cast(infos, _p),
+                                         _stream(stream))
+        _check(st, (ED_OK, ED_ENOCONV) if allow_noconv else (ED_OK,))
+        return ev, [i.as_dict() for i in infos][k0:]
+
     def lanczos_tridiag(self, v0, m: int, opts=None, ws=None, stream=None):
         """(alpha, beta, ||v0||^2): k <= m tridiagonal Lanczos coefficients from v0."""
         import torch
@@ -421,15 +440,16 @@ def green_function(H0: "Hamiltonian", e0: float, psi0, Hp: "Hamiltonian", Hm: "H
 def lowest_levels(hams: Sequence["Hamiltonian"], K: int, opts=None, seed: int = 1, kmax: int = 200, progress=None):
     """The K lowest levels, counted with multiplicity, over the sectors `hams`
     (the thermal set behind Eq. 3).  Ground energies of every sector come from
-    one batched run (ed_lanczos_ground_batched); then, while some sector's
-    highest computed level lies at or below the K-th lowest level found so
-    far, that sector's level count is doubled (ed_arnoldi_lowest), since only
-    such a sector can hold another of the K.  Returns (levels, vectors,
-    details): levels = [(E, sector index, level index)] ascending (the K
-    lowest, more where a multiplet straddles the K-th), vectors = {sector
-    index: DEVICE tensor [k, D]} for the sectors with a level in the list,
-    details = counts and the sectors capped at kmax.  progress: optional
-    callable taking one line of text after each round."""
+    one batched run (ed_lanczos_ground_batched).  Then, as long as some sector
+    that still has levels left has its highest computed level at or below the
+    K-th lowest level found so far, the one whose highest level is lowest gets
+    more levels (ed_arnoldi_lowest, then ed_arnoldi_lowest_more on top of the
+    converged ones): only such a sector can hold another of the K.  Returns
+    (levels, vectors, details): levels = [(E, sector index, level index)]
+    ascending (the K lowest, more where a multiplet straddles the K-th),
+    vectors = {sector index: DEVICE tensor [k, D]} for the sectors with a level
+    in the list, details = counts and the sectors capped at kmax.  progress:
+    optional callable taking one line of text every 50 extensions."""
     import torch
     n = len(hams)
     E0, _ = lanczos_ground_batched(hams, opts, seed=seed)
@@ -437,7 +457,7 @@ def lowest_levels(hams: Sequence["Hamiltonian"], K: int, opts=None, seed: int = 
     vecs = {}
     calls = 0
 
-    def solve(s, k):
+    def extend(s, k):
         nonlocal calls
         H = hams[s]
         dt = torch.float64 if H.precision == ED_FP64 else torch.float32
@@ -445,7 +465,12 @@ def lowest_levels(hams: Sequence["Hamiltonian"], K: int, opts=None, seed: int = 
         fill_random(v0, seed + s, 1)
         ev = torch.empty((k, H.D), dtype=dt, device="cuda")
         try:
-            E, _ = H.lowest(k, v0, opts, evecs=ev)
+            if s in vecs:
+                k0 = vecs[s].shape[0]
+                ev[:k0].copy_(vecs[s])
+                E, _ = H.lowest_more(k0, k, energies[s], v0, ev, opts)
+            else:
+                E, _ = H.lowest(k, v0, opts, evecs=ev)
         except EDError as err:
             raise EDError(err.status, "sector %d (D=%d), k=%d: %s" % (s, H.D, k, err)) from None
         energies[s] = [float(e) for e in E]   # discovery order (ascending up to rounding) = row order
@@ -459,19 +484,23 @@ def lowest_levels(hams: Sequence["Hamiltonian"], K: int, opts=None, seed: int = 
     capped = set()
     while True:
         T = threshold()
-        grow = [s for s in range(n) if max(energies[s]) <= T and len(energies[s]) < min(hams[s].D, kmax)]
-        if not grow:
-            break
-        for s in grow:
-            solve(s, min(hams[s].D, kmax, 2 * len(energies[s])))
-            if len(energies[s]) == kmax and max(energies[s]) <= T:
+        cand = [s for s in range(n) if max(energies[s]) <= T]
+        for s in cand:
+            if len(energies[s]) >= min(hams[s].D, kmax) and len(energies[s]) < hams[s].D:
                 capped.add(s)
-        if progress:
-            progress("lowest_levels: %d sectors grown below %.6g, %d lowest calls" % (len(grow), T, calls))
+        cand = [s for s in cand if len(energies[s]) < min(hams[s].D, kmax)]
+        if not cand:
+            break
+        s = min(cand, key=lambda q: max(energies[q]))
+        k = len(energies[s]) if s in vecs else 0
+        extend(s, min(hams[s].D, kmax, k + max(2, k // 4)))
+        if progress and calls % 50 == 0:
+            progress("lowest_levels: %d extensions, K-th level %.6g" % (calls, T))
     T = threshold()
     levels = sorted((e, s, i) for s, es in energies.items() for i, e in enumerate(es) if e <= T)
     for s in sorted({s for _, s, _ in levels} - set(vecs)):
-        solve(s, 1)                  # one-level sectors: ground energy known, vector not yet
+        extend(s, 1)                 # one-level sectors: ground energy known, vector not yet
+    levels = sorted((e, s, i) for s, es in energies.items() for i, e in enumerate(es) if e <= T)
     return levels, {s: vecs[s] for s in {s for _, s, _ in levels}}, {"lowest_calls": calls,
                                                                     "capped": sorted(capped), "threshold": T}
 

@@ -157,20 +157,25 @@ def test_generic_model_ground_state():
     assert _rel(E, e_ref) <= 1e-10
 
 
+@pytest.mark.parametrize("keep", [0, 10], ids=["ritz_restart", "implicit_restart"])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("name,phys,nn,k", [
     ("kanatom_bath", wl.kanamori(3, 1, 2.3, 0.4, seed=2), (3, 3), 8),
     ("hub2x3", wl.hubbard(3, 2, 1.0, 4.0), (3, 3), 6),
     ("kan9_32", wl.kanamori(3, 2, 2.3, 0.4, seed=6), (3, 2), 5),
-], ids=["kanatom_bath", "hub2x3", "kan9_32"])
-def test_lowest_k_with_multiplicity(name, phys, nn, k, prec):
+    ("kan9_32_k24", wl.kanamori(3, 2, 2.3, 0.4, seed=6), (3, 2), 24),
+], ids=["kanatom_bath", "hub2x3", "kan9_32", "kan9_32_k24"])
+def test_lowest_k_with_multiplicity(name, phys, nn, k, prec, keep):
     ed = gpu_ed()
     b, H = build(phys, *nn, prec)
     sec = sector(phys, *nn)
     ev = np.linalg.eigvalsh(sec.dense())[:k]
     evecs = torch.empty((k, b.D), dtype=torch.float64 if prec == 0 else torch.float32, device=DEV)
-    got, infos = H.lowest(k, _v0(b.D, prec), ed.options(tol=1e-10 if prec == 0 else 1e-7, max_basis=60),
-                          evecs=evecs)
+    mb = 60 if keep == 0 else 30
+    got, infos = H.lowest(k, _v0(b.D, prec), ed.options(tol=1e-10 if prec == 0 else 1e-7, max_basis=mb, keep=keep,
+                                                        max_iter=20000), evecs=evecs)
+    if keep:
+        assert sum(i["restarts"] for i in infos) > 0
     tol = 1e-9 if prec == 0 else 1e-6
     np.testing.assert_allclose(np.sort(got), ev, atol=tol * max(1.0, abs(ev[0])))
     V = evecs.double().cpu().numpy()
@@ -244,3 +249,28 @@ def test_config2_lowest_3_fp32_vs_golden():
     got, infos = H.lowest(3, _v0(b.D, 1, wl.start_vector_seed(2)), ed.options(tol=1e-7, max_basis=80))
     for g, r in zip(np.sort(got), ev[:3]):
         assert _rel(g, r) <= 1e-6, (got, ev)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_lowest_more_continues_from_converged_levels(prec):
+    """ed_arnoldi_lowest_more on top of 4 levels gives the same 10 lowest as the
+    dense spectrum, with the first 4 vectors left untouched."""
+    ed = gpu_ed()
+    phys, nn = wl.kanamori(3, 2, 2.3, 0.4, seed=6), (3, 2)
+    b, H = build(phys, *nn, prec)
+    ev = np.linalg.eigvalsh(sector(phys, *nn).dense())[:10]
+    dt = torch.float64 if prec == 0 else torch.float32
+    o = ed.options(tol=1e-10 if prec == 0 else 1e-7, max_basis=30, keep=10, max_iter=20000)
+    e4 = torch.empty((4, b.D), dtype=dt, device=DEV)
+    E4, _ = H.lowest(4, _v0(b.D, prec), o, evecs=e4)
+    e10 = torch.empty((10, b.D), dtype=dt, device=DEV)
+    e10[:4].copy_(e4)
+    E10, infos = H.lowest_more(4, 10, E4, _v0(b.D, prec), e10, o)
+    assert len(infos) == 6
+    assert torch.equal(e10[:4], e4)
+    tol = 1e-9 if prec == 0 else 1e-6
+    np.testing.assert_allclose(np.sort(E10), ev, atol=tol * max(1.0, abs(ev[0])))
+    V = e10.double().cpu().numpy()
+    assert np.max(np.abs(V @ V.T - np.eye(10))) < (1e-8 if prec == 0 else 1e-4)
+    with pytest.raises(ed.EDError):
+        H.lowest_more(10, 10, E10, _v0(b.D, prec), e10, o)
