@@ -238,7 +238,7 @@ def thermal_bench(K=300, beta=58.0, cutoff=1e-5, m=100):
     iteration: the K = 300 lowest levels over all 169 sectors, Boltzmann
     weights at beta (T = 200 K with energies in eV) with the 1e-5 cut, and the
     Green function of Eq. 3 (spin up, first impurity orbital) from every kept
-    level at 64 Matsubara points.  FP64 vectors."""
+    level at 64 Matsubara points.  FP64 vectors, then FP32-mixed ones."""
     import numpy as np
     import torch
     from paper_1004_3354_amd import ed, models
@@ -246,36 +246,43 @@ def thermal_bench(K=300, beta=58.0, cutoff=1e-5, m=100):
     p = models.params_from_model(phys)
     ns = int(phys["Ns"])
     z = 1j * np.pi * (2 * np.arange(64) + 1) / beta
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hams = [ed.Hamiltonian(p, ed.Basis(ns, u, d), ed.ED_FP64) for (u, d) in sectors]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    opts = ed.options(tol=1e-8, max_iter=20000, max_basis=48, keep=16)
-    levels, vecs, det = ed.lowest_levels(hams, K, opts, progress=log)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    w, kept = ed.boltzmann_weights([e for e, _, _ in levels], beta, cutoff)
-    g = np.zeros(len(z), dtype=np.complex128)
-    byn = {tuple(sec): h for sec, h in zip(sectors, hams)}
-    for (e, s, i), wi in zip(levels, w):
-        if wi == 0.0:
-            continue
-        u, d = sectors[s]
-        ed.green_function(hams[s], e, vecs[s][i], byn.get((u + 1, d)), byn.get((u - 1, d)), 0, 0, z, m=m,
-                          weight=wi, g=g)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    out = {"workload": "kanamori_Ns12_3orb_9bath_all169", "K": K, "beta": beta, "cutoff": cutoff, "m": m,
-           "tables_s": round(t1 - t0, 3), "levels_s": round(t2 - t1, 3), "green_s": round(t3 - t2, 3),
-           "total_s": round(t3 - t0, 3), "levels_found": len(levels), "kept_levels": kept,
-           "lowest_calls": det["lowest_calls"], "capped": det["capped"],
-           "level_span": round(levels[K - 1][0] - levels[0][0], 6),
-           "sectors_with_levels": len(vecs), "G_iw0": [float(g[0].real), float(g[0].imag)]}
-    log("thermal N_s=12: levels %.2f s (%d lowest calls), Green %.2f s over %d levels" %
-        (t2 - t1, det["lowest_calls"], t3 - t2, kept))
-    del hams, vecs
-    torch.cuda.empty_cache()
+    out = {"workload": "kanamori_Ns12_3orb_9bath_all169", "K": K, "beta": beta, "cutoff": cutoff, "m": m}
+    gref = None
+    for key, prec, tol in (("fp64", ed.ED_FP64, 1e-8), ("fp32_mixed", ed.ED_FP32, 1e-7)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hams = [ed.Hamiltonian(p, ed.Basis(ns, u, d), prec) for (u, d) in sectors]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        opts = ed.options(tol=tol, max_iter=20000, max_basis=48, keep=16)
+        levels, vecs, det = ed.lowest_levels(hams, K, opts, progress=log)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        w, kept = ed.boltzmann_weights([e for e, _, _ in levels], beta, cutoff)
+        g = np.zeros(len(z), dtype=np.complex128)
+        byn = {tuple(sec): h for sec, h in zip(sectors, hams)}
+        for (e, s, i), wi in zip(levels, w):
+            if wi == 0.0:
+                continue
+            u, d = sectors[s]
+            ed.green_function(hams[s], e, vecs[s][i], byn.get((u + 1, d)), byn.get((u - 1, d)), 0, 0, z, m=m,
+                              weight=wi, g=g)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        r = {"tables_s": round(t1 - t0, 3), "levels_s": round(t2 - t1, 3), "green_s": round(t3 - t2, 3),
+             "total_s": round(t3 - t0, 3), "levels_found": len(levels), "kept_levels": kept,
+             "lowest_calls": det["lowest_calls"], "capped": det["capped"],
+             "level_span": round(levels[K - 1][0] - levels[0][0], 6), "E_min": levels[0][0],
+             "sectors_with_levels": len(vecs)}
+        if gref is None:
+            gref = g
+        else:
+            r["G_max_rel_dev_vs_fp64"] = float(np.max(np.abs(g - gref)) / np.max(np.abs(gref)))
+        out[key] = r
+        log("thermal N_s=12 %s: levels %.2f s (%d lowest calls), Green %.2f s over %d levels" %
+            (key, t2 - t1, det["lowest_calls"], t3 - t2, kept))
+        del hams, vecs, byn
+        torch.cuda.empty_cache()
     return out
 
 
