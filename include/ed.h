@@ -54,7 +54,7 @@ typedef enum {
 enum { ED_FP64 = 0, ED_FP32 = 1 };
 enum { ED_SPIN_UP = 0, ED_SPIN_DN = 1 };
 /* Four-fermion impurity terms of the multi-orbital Hamiltonian (Section 4). */
-enum { ED_SPIN_FLIP = 1, ED_PAIR_HOP = 2, ED_UD_GENERAL = 3 };
+enum { ED_SPIN_FLIP = 1, ED_PAIR_HOP = 2, ED_UD_GENERAL = 3, ED_UU_GENERAL = 4, ED_DD_GENERAL = 5 };
 
 typedef struct ed_basis_s *ed_basis_t;
 typedef struct ed_ham_s *ed_ham_t;
@@ -105,23 +105,26 @@ void ed_basis_free(ed_basis_t b);
  * as in the paper (so the Kanamori term -J'[...] has coef = -J'), or
  * (ED_UD_GENERAL) the general opposite-spin two-body string
  * c+_{m up} c+_{m' dn} c_{l dn} c_{k up}: the element U_{m m' k l} of a full
- * U-matrix, whose other non-diagonal elements Section 4 closes on.
+ * U-matrix, whose other non-diagonal elements Section 4 closes on, or
+ * (ED_UU_GENERAL, ED_DD_GENERAL) the same-spin string c+_{m s} c+_{m' s} c_{l s} c_{k s}.
  * Requirements (else EINVAL): every value finite; hop[s] symmetric with a zero
  * diagonal (on-site energies belong in eps); w_ss zero on and below the
  * diagonal; for x of type ED_SPIN_FLIP or ED_PAIR_HOP: m != m', both < Ns, the
  * list Hermitian (the summed coefficient of (type, m, m') equals that of
  * (type, m', m)); for ED_UD_GENERAL: m, m', k, l < Ns (any may coincide; k = m
  * or l = m' give density-assisted terms) and the summed coefficient of
- * (m, m', k, l) equal to that of (k, l, m, m').  Off-diagonal w_ud entries may touch at most 8 sites
+ * (m, m', k, l) equal to that of (k, l, m, m'); for ED_UU/DD_GENERAL: indices
+ * < Ns, m != m', k != l, {m, m'} != {k, l} (density terms belong in w_ss) and
+ * the same Hermitian pairing after ordering each pair (a swap is a sign).  Off-diagonal w_ud entries may touch at most 8 sites
  * (else EUNSUPPORTED).  Input arrays are read during the call only.
  */
 typedef struct {
-    int32_t type;   /* ED_SPIN_FLIP, ED_PAIR_HOP or ED_UD_GENERAL */
+    int32_t type;   /* ED_SPIN_FLIP, ED_PAIR_HOP, ED_UD_GENERAL, ED_UU_GENERAL, ED_DD_GENERAL */
     int32_t m;
     int32_t mp;
     double coef;
-    int32_t k;      /* ED_UD_GENERAL only (ignored otherwise) */
-    int32_t l;      /* ED_UD_GENERAL only (ignored otherwise) */
+    int32_t k;      /* general terms only (ignored otherwise) */
+    int32_t l;      /* general terms only (ignored otherwise) */
 } ed_xterm;
 
 typedef struct {

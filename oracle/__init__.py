@@ -124,7 +124,9 @@ def terms_generic(ns: int, eps, hop, w_ud, w_ss, xterms: Iterable = ()) -> List[
     in the multi-orbital Hamiltonian of Section 4)
     + sum over (3, i, j, k, l, c) of c * c+_{i up} c+_{j dn} c_{l dn} c_{k up}, an
     opposite-spin element U_ijkl of a full two-body U-matrix (Section 4's
-    closing remark on the other non-diagonal elements)."""
+    closing remark on the other non-diagonal elements)
+    + sum over (4 or 5, i, j, k, l, c) of c * c+_{i s} c+_{j s} c_{l s} c_{k s},
+    a same-spin element (s = up for 4, down for 5)."""
     eps = np.asarray(eps, dtype=np.float64).reshape(2, ns)
     hop = np.asarray(hop, dtype=np.float64).reshape(2, ns, ns)
     w_ud = np.asarray(w_ud, dtype=np.float64).reshape(ns, ns)
@@ -153,6 +155,11 @@ def terms_generic(ns: int, eps, hop, w_ud, w_ss, xterms: Iterable = ()) -> List[
         if xt[0] == UD_GENERAL:
             _, i, j, k, l, c = xt
             T.append((float(c), [(_up(i, ns), 1), (_dn(j, ns), 1), (_dn(l, ns), 0), (_up(k, ns), 0)]))
+        elif xt[0] in (UU_GENERAL, DD_GENERAL):
+            t, i, j, k, l, c = xt
+            sp = 0 if t == UU_GENERAL else 1
+            T.append((float(c), [(_mode(i, sp, ns), 1), (_mode(j, sp, ns), 1), (_mode(l, sp, ns), 0),
+                                 (_mode(k, sp, ns), 0)]))
         else:
             typ, m, mp, c = xt
             T.append((float(c), _xstring(typ, m, mp, ns)))
@@ -162,6 +169,8 @@ def terms_generic(ns: int, eps, hop, w_ud, w_ss, xterms: Iterable = ()) -> List[
 SPIN_FLIP = 1
 PAIR_HOP = 2
 UD_GENERAL = 3
+UU_GENERAL = 4
+DD_GENERAL = 5
 
 
 def _xstring(typ: int, m: int, mp: int, ns: int) -> List[Tuple[int, int]]:

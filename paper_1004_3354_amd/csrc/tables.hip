@@ -54,7 +54,27 @@ __global__ void k_scan_i64(const int64_t *in, int64_t *out, int64_t n) {
 }
 
 // ------------------------------------------------------------ hop tables ----
-__global__ void k_hop_count(const uint32_t *st, int64_t dim, const int2 *pairs, int np, int64_t *cnt) {
+// Same-spin two-body string c+_i c+_j c_l c_k (q = (i, j, k, l)) on a one-spin
+// word: the operators act right to left, each contributing (-1)^(occupied
+// modes below it); false when one of them annihilates the state.
+__device__ __forceinline__ bool two_body_move(uint32_t s, int4 q, uint32_t *out, int *neg) {
+    const int pos[4] = {q.z, q.w, q.y, q.x};
+    const bool cre[4] = {false, false, true, true};
+    int par = 0;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const uint32_t b = 1u << pos[o];
+        if (((s & b) != 0u) == cre[o]) return false;
+        par += __popc(s & (b - 1u));
+        s ^= b;
+    }
+    *out = s;
+    *neg = par & 1;
+    return true;
+}
+
+__global__ void k_hop_count(const uint32_t *st, int64_t dim, const int2 *pairs, int np, const int4 *quads, int nq,
+                            int64_t *cnt) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < dim;
          r += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t s = st[r];
@@ -63,12 +83,18 @@ __global__ void k_hop_count(const uint32_t *st, int64_t dim, const int2 *pairs, 
             const int i = pairs[q].x, j = pairs[q].y;
             c += ((s >> j) & 1u) && !((s >> i) & 1u);
         }
+        for (int q = 0; q < nq; ++q) {
+            uint32_t s2;
+            int ng;
+            c += two_body_move(s, quads[q], &s2, &ng) ? 1 : 0;
+        }
         cnt[r] = c;
     }
 }
 
 __global__ void k_hop_fill(const uint32_t *st, int64_t dim, int ns, int n, const int2 *pairs,
-                           const double *pamp, int np, const int64_t *off64, int32_t *off,
+                           const double *pamp, int np, const int4 *quads, const double *qamp, int nq,
+                           const int64_t *off64, int32_t *off,
                            int32_t *tgt, int8_t *sgn, double *amp, double *sa64, float *sa32) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < dim;
          r += (int64_t)gridDim.x * blockDim.x) {
@@ -94,6 +120,23 @@ __global__ void k_hop_fill(const uint32_t *st, int64_t dim, int ns, int n, const
             tgt[p] = t;
             sgn[p] = sg;
             amp[p] = pamp[q];
+            ++k;
+        }
+        for (int q = 0; q < nq; ++q) {
+            uint32_t s2;
+            int ng;
+            if (!two_body_move(s, quads[q], &s2, &ng)) continue;
+            const int32_t t = (int32_t)rank_state(s2, ns, n);
+            int64_t p = k;
+            while (p > a && tgt[p - 1] > t) {
+                tgt[p] = tgt[p - 1];
+                sgn[p] = sgn[p - 1];
+                amp[p] = amp[p - 1];
+                --p;
+            }
+            tgt[p] = t;
+            sgn[p] = ng ? (int8_t)-1 : (int8_t)1;
+            amp[p] = qamp[q];
             ++k;
         }
         for (int64_t e = a; e < k; ++e) {
@@ -273,14 +316,26 @@ static void build_spin(ed_ham_s *h, int s, const BasisData &b, const ed_params *
                 pairs.push_back(make_int2(i, j));
                 pamp.push_back(hs[i * ns + j]);
             }
-    DevMem dpairs, dpamp, cnt, off64;
+    // same-spin two-body terms of this spin, (i, j, k, l) for c+_i c+_j c_l c_k
+    std::vector<int4> quads;
+    std::vector<double> qamp;
+    for (int t2 = 0; t2 < p->n_x; ++t2) {
+        const ed_xterm &x = p->x[t2];
+        if (x.type == (s == 0 ? ED_UU_GENERAL : ED_DD_GENERAL)) {
+            quads.push_back(make_int4(x.m, x.mp, x.k, x.l));
+            qamp.push_back(x.coef);
+        }
+    }
+    DevMem dpairs, dpamp, dquads, dqamp, cnt, off64;
     upload(dpairs, pairs);
     upload(dpamp, pamp);
+    upload(dquads, quads);
+    upload(dqamp, qamp);
     cnt.alloc((size_t)dim * sizeof(int64_t));
     off64.alloc((size_t)(dim + 1) * sizeof(int64_t));
     const unsigned g = grid_for(dim, 256, 1 << 16);
-    k_hop_count<<<g, 256>>>(t.states.as<uint32_t>(), dim, dpairs.as<int2>(), (int)pairs.size(),
-                            cnt.as<int64_t>());
+    k_hop_count<<<g, 256>>>(t.states.as<uint32_t>(), dim, dpairs.as<int2>(), (int)pairs.size(), dquads.as<int4>(),
+                            (int)quads.size(), cnt.as<int64_t>());
     ED_LAUNCH_CHECK();
     k_scan_i64<<<1, 1024>>>(cnt.as<int64_t>(), off64.as<int64_t>(), dim);
     ED_LAUNCH_CHECK();
@@ -295,7 +350,8 @@ static void build_spin(ed_ham_s *h, int s, const BasisData &b, const ed_params *
     t.sa64.alloc((size_t)nnz * sizeof(double));
     t.sa32.alloc((size_t)nnz * sizeof(float));
     k_hop_fill<<<g, 256>>>(t.states.as<uint32_t>(), dim, ns, t.n, dpairs.as<int2>(), dpamp.as<double>(),
-                           (int)pairs.size(), off64.as<int64_t>(), t.off.as<int32_t>(), t.tgt.as<int32_t>(),
+                           (int)pairs.size(), dquads.as<int4>(), dqamp.as<double>(), (int)quads.size(),
+                           off64.as<int64_t>(), t.off.as<int32_t>(), t.tgt.as<int32_t>(),
                            t.sgn.as<int8_t>(), t.amp.as<double>(), t.sa64.as<double>(), t.sa32.as<float>());
     ED_LAUNCH_CHECK();
 
@@ -494,6 +550,7 @@ static void build_xterms(ed_ham_s *h, const ed_params *p) {
     std::map<std::pair<int, int>, double> acc;  // (up move, dn move) -> amplitude
     for (int t = 0; t < p->n_x; ++t) {
         const ed_xterm &x = p->x[t];
+        if (x.type == ED_UU_GENERAL || x.type == ED_DD_GENERAL) continue;  // in the one-spin tables
         if (x.type == ED_UD_GENERAL) {
             acc[{move_index(h->sp[0], x.k, x.m), move_index(h->sp[1], x.l, x.mp)}] += x.coef;
             continue;
@@ -609,13 +666,27 @@ static void validate(const ed_params *p, int ns) {
     }
     std::map<std::tuple<int, int, int>, double> sum;
     std::map<std::tuple<int, int, int, int>, double> gsum;
+    std::map<std::tuple<int, int, int>, double> ssum;
     for (int t = 0; t < p->n_x; ++t) {
         const ed_xterm &x = p->x[t];
-        if (x.type == ED_UD_GENERAL) {
+        if (x.type == ED_UD_GENERAL || x.type == ED_UU_GENERAL || x.type == ED_DD_GENERAL) {
             for (int q : {x.m, x.mp, x.k, x.l})
                 if (q < 0 || q >= ns) fail(ED_EINVAL, "ed_ham_create: general term index %d outside [0, Ns)", q);
             if (!std::isfinite(x.coef)) fail(ED_EINVAL, "ed_ham_create: non-finite term coefficient");
-            gsum[std::make_tuple(x.m, x.mp, x.k, x.l)] += x.coef;
+            if (x.type == ED_UD_GENERAL) {
+                gsum[std::make_tuple(x.m, x.mp, x.k, x.l)] += x.coef;
+                continue;
+            }
+            // same spin: c+_i c+_j c_l c_k, i != j, k != l, not a density term;
+            // the pair orders are normalised (i < j, k < l, each swap a sign)
+            if (x.m == x.mp || x.k == x.l)
+                fail(ED_EINVAL, "ed_ham_create: same-spin term (%d,%d,%d,%d) repeats a mode", x.m, x.mp, x.k, x.l);
+            const int i = std::min(x.m, x.mp), j = std::max(x.m, x.mp);
+            const int k = std::min(x.k, x.l), l = std::max(x.k, x.l);
+            if (i == k && j == l)
+                fail(ED_EINVAL, "ed_ham_create: same-spin density term (%d,%d): put it in w_ss", i, j);
+            const double sg = ((x.m > x.mp) != (x.k > x.l)) ? -1.0 : 1.0;
+            ssum[std::make_tuple(x.type, i * 32 + j, k * 32 + l)] += sg * x.coef;
             continue;
         }
         if (x.type != ED_SPIN_FLIP && x.type != ED_PAIR_HOP) fail(ED_EINVAL, "ed_ham_create: bad term type %d", x.type);
@@ -637,6 +708,11 @@ static void validate(const ed_params *p, int ns) {
         auto it = gsum.find(std::make_tuple(k, l, i, j));
         if ((it == gsum.end() ? 0.0 : it->second) != kv.second)
             fail(ED_EINVAL, "ed_ham_create: general terms are not Hermitian at (%d, %d, %d, %d)", i, j, k, l);
+    }
+    for (auto &kv : ssum) {
+        auto it = ssum.find(std::make_tuple(std::get<0>(kv.first), std::get<2>(kv.first), std::get<1>(kv.first)));
+        if ((it == ssum.end() ? 0.0 : it->second) != kv.second)
+            fail(ED_EINVAL, "ed_ham_create: same-spin general terms are not Hermitian (type %d)", std::get<0>(kv.first));
     }
 }
 

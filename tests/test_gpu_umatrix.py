@@ -1,5 +1,6 @@
-"""General opposite-spin U-matrix terms c+_{i up} c+_{j dn} c_{l dn} c_{k up}
-(beyond the spin-flip and pair-hopping terms of Section 4) on the GPU against
+"""General U-matrix terms, opposite-spin c+_{i up} c+_{j dn} c_{l dn} c_{k up}
+and same-spin c+_{i s} c+_{j s} c_{l s} c_{k s} (beyond the spin-flip and
+pair-hopping terms of Section 4), on the GPU against
 the oracle: H.v for every schedule that applies, within the summation bound,
 and the ground-state energy (FP64 1e-10, FP32-mixed 1e-6)."""
 import numpy as np
@@ -13,6 +14,20 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 UD = 3
+
+
+def same_spin_terms(ns, seed, nterms=6):
+    """Random Hermitian pairs of same-spin two-body terms of both spins."""
+    rng = np.random.default_rng(seed + 200)
+    xt = []
+    while len(xt) < 2 * nterms:
+        t = 4 + int(rng.integers(0, 2))
+        i, j, k, l = (int(v) for v in rng.integers(0, ns, 4))
+        if i == j or k == l or {i, j} == {k, l}:
+            continue
+        c = float(rng.uniform(-0.5, 0.5))
+        xt += [(t, i, j, k, l, c), (t, k, l, i, j, c)]
+    return xt
 
 
 def umatrix_model(ns, seed, nterms=10, stays=True):
@@ -70,6 +85,14 @@ def test_apply_general_terms(ns, nup, ndn, seed, stays, prec):
     _check_apply(umatrix_model(ns, seed, stays=stays), ns, nup, ndn, prec, seed)
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("ns,nup,ndn,seed", [(6, 3, 2, 21), (8, 4, 4, 22), (10, 5, 4, 23), (9, 1, 8, 24)])
+def test_apply_same_spin_terms(ns, nup, ndn, seed, prec):
+    p = umatrix_model(ns, seed)
+    p["xterms"] = list(p["xterms"]) + same_spin_terms(ns, seed)
+    _check_apply(p, ns, nup, ndn, prec, seed)
+
+
 def test_apply_general_terms_only_on_impurity_sites():
     """Terms confined to the three lowest sites keep the packed down-move words."""
     ns = 9
@@ -90,6 +113,7 @@ def test_ground_state_general_terms(prec):
     ed = gpu_ed()
     ns, nup, ndn = 8, 4, 4
     p = umatrix_model(ns, 11)
+    p["xterms"] = list(p["xterms"]) + same_spin_terms(ns, 11)
     H, sec = _check_apply(p, ns, nup, ndn, prec, 12)
     e_ref = np.linalg.eigvalsh(sec.dense())[0]
     v0 = torch.empty(H.D, dtype=torch.float64 if prec == 0 else torch.float32, device=DEV)
@@ -105,7 +129,11 @@ def test_general_terms_validation():
     b = ed.Basis(ns, 3, 3)
     for xt in ([(UD, 0, 1, 2, 3, 0.5)],                                  # partner missing
                [(UD, 0, 1, 2, 3, 0.5), (UD, 2, 3, 0, 1, 0.4)],           # partner with another value
-               [(UD, 0, 1, 2, 6, 0.5), (UD, 2, 6, 0, 1, 0.5)]):          # index outside [0, Ns)
+               [(UD, 0, 1, 2, 6, 0.5), (UD, 2, 6, 0, 1, 0.5)],           # index outside [0, Ns)
+               [(4, 0, 0, 1, 2, 0.5), (4, 1, 2, 0, 0, 0.5)],             # repeated creator
+               [(5, 0, 1, 1, 0, 0.5)],                                   # a density term
+               [(4, 0, 1, 2, 3, 0.5), (4, 2, 3, 0, 1, -0.5)],            # partner with the wrong sign
+               [(5, 0, 1, 2, 3, 0.5)]):                                  # partner missing
         q = dict(p)
         q["xterms"] = xt
         with pytest.raises(ed.EDError) as ei:

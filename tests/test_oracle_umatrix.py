@@ -50,3 +50,25 @@ def test_hermitian_set_is_symmetric_and_one_sided_is_not():
     assert np.max(np.abs(H - H.T)) < 1e-15 and np.abs(H).sum() > 0
     H1 = _dense([(orc.UD_GENERAL, 0, 1, 2, 3, 0.5)], nup=2, ndn=2)   # hermitian partner missing
     assert np.max(np.abs(H1 - H1.T)) > 0.1
+
+
+def test_same_spin_term_reduces_to_density_and_hops():
+    """For j distinct from i and k the same-spin string with l = j is
+    c+_i c+_j c_j c_k = c+_i n_j c_k = c+_i c_k n_j, a density-assisted hop;
+    with its Hermitian partner the matrix is symmetric."""
+    i, j, k = 0, 2, 3
+    for t, sp in ((orc.UU_GENERAL, 0), (orc.DD_GENERAL, 1)):
+        a = _dense([(t, i, j, k, j, 0.8), (t, k, j, i, j, 0.8)], nup=2, ndn=2)
+        z = np.zeros
+        T = [(0.8, [(orc._mode(i, sp, NS), 1), (orc._mode(k, sp, NS), 0)] + orc._number(orc._mode(j, sp, NS))),
+             (0.8, [(orc._mode(k, sp, NS), 1), (orc._mode(i, sp, NS), 0)] + orc._number(orc._mode(j, sp, NS)))]
+        b = orc.Sector(NS, 2, 2, T).dense()
+        assert np.array_equal(a, b) and np.abs(a).sum() > 0
+        assert np.max(np.abs(a - a.T)) == 0.0
+
+
+def test_same_spin_pair_antisymmetry():
+    """Swapping the two creators (or the two annihilators) flips the sign."""
+    H1 = _dense([(orc.UU_GENERAL, 0, 1, 2, 3, 0.5), (orc.UU_GENERAL, 2, 3, 0, 1, 0.5)], nup=2, ndn=1)
+    H2 = _dense([(orc.UU_GENERAL, 1, 0, 2, 3, -0.5), (orc.UU_GENERAL, 2, 3, 1, 0, -0.5)], nup=2, ndn=1)
+    assert np.array_equal(H1, H2) and np.abs(H1).sum() > 0
