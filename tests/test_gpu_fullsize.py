@@ -68,3 +68,45 @@ def test_fullsize_sampled_rows(cfg, prec):
         worst = max(worst, abs(g - ref) / tol)
         assert abs(g - ref) <= tol, (int(J), g, ref, tol, sched)
     print("cfg%d prec%d schedule %s: %d rows, worst err/bound %.3f" % (cfg, prec, sched, len(rows), worst))
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_fullsize_general_terms_sampled_rows(prec):
+    """The N_s = 15 workload plus general U-matrix elements (opposite- and
+    same-spin, on impurity and bath sites), sampled rows in the tuned schedule."""
+    from paper_1004_3354_amd import models
+    ed = gpu_ed()
+    phys, sectors = wl.config(2)
+    nup, ndn = sectors[0]
+    ns = int(phys["Ns"])
+    p = models.params_from_model(phys)
+    xt = list(p.get("xterms", []))
+    for (t, i, j, k, l, c) in [(3, 0, 1, 2, 0, 0.21), (3, 1, 5, 9, 1, -0.13), (3, 2, 2, 0, 0, 0.08),
+                               (4, 0, 1, 2, 9, 0.11), (5, 1, 2, 0, 5, -0.07), (4, 0, 3, 0, 7, 0.05)]:
+        xt += [(t, i, j, k, l, c), (t, k, l, i, j, c)]
+    p = dict(p, xterms=xt)
+    b = ed.Basis(ns, nup, ndn)
+    H = ed.Hamiltonian(p, b, prec)
+    dt = torch.float64 if prec == 0 else torch.float32
+    x = torch.empty(b.D, dtype=dt, device="cuda")
+    ed.fill_random(x, SEED + 7, 0)
+    y = torch.empty_like(x)
+    H.apply(x, y)
+    H.apply(x, y)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    rows = _rows(b.dup, b.ddn, ns, ndn, rng, nrand=800)
+    yg = y[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    sched = ed.variant_name(H.current_variant())
+    del x, y
+    torch.cuda.empty_cache()
+    sec = orc.Sector(ns, nup, ndn, orc.terms_generic(ns, p["eps"], p["hop"], p["w_ud"], p["w_ss"], xt))
+    u = U64 if prec == 0 else U32
+    for J, g in zip(rows, yg):
+        cols, vals = sec.row_entries(int(J))
+        xv = wl.uniform_at(SEED + 7, cols.astype(np.uint64))
+        if prec == 1:
+            xv = xv.astype(np.float32).astype(np.float64)
+        ref = float(np.dot(vals, xv))
+        tol = (len(cols) + 8) * u * float(np.dot(np.abs(vals), np.abs(xv))) + 1e-300
+        assert abs(g - ref) <= tol, (int(J), g, ref, tol, sched)
