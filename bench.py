@@ -254,7 +254,7 @@ def thermal_bench(K=300, beta=58.0, cutoff=1e-5, m=100):
         hams = [ed.Hamiltonian(p, ed.Basis(ns, u, d), prec) for (u, d) in sectors]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        opts = ed.options(tol=tol, max_iter=20000, max_basis=48, keep=16)
+        opts = ed.options(tol=tol, max_iter=20000, max_basis=20, keep=8)
         levels, vecs, det = ed.lowest_levels(hams, K, opts, progress=log)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
