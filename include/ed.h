@@ -191,7 +191,11 @@ void ed_ham_free(ed_ham_t h);
  * restarts when the stored basis is full. */
 typedef struct {
     int32_t max_iter;     /* total Lanczos steps over all restarts (default 600)    */
-    int32_t max_basis;    /* stored basis vectors before a restart (default 120)    */
+    int32_t max_basis;    /* stored basis vectors before a restart; 0 (default) =
+                             planned: the largest basis of at most 120 vectors whose
+                             workspace fits the free device memory (less a reserve
+                             of max(1 GiB, 2 % of the device)) in ed_workspace_bytes,
+                             or the given workspace in the solvers                  */
     double tol;           /* stop when |beta_j s_j| <= tol * max(|theta|, 1) (1e-10) */
     int32_t reorth;       /* Gram-Schmidt per step (default 2): 0 = three-term only, 1 = one
                              full pass, 2 = two full passes (CGS2), 3 = the two projections
@@ -216,13 +220,23 @@ typedef struct {
     double residual;      /* ||H psi - E psi|| / ||psi|| of the returned vector  */
     double ritz;          /* Ritz value from the tridiagonal matrix             */
     double rq_fp64;       /* FP64 Rayleigh quotient (equals the reported E)     */
+    double gap_lower;     /* eta: second Ritz value of the last cycle minus its
+                             residual bound, taken as a lower bound on the next
+                             eigenvalue (of the deflated operator); NaN if none   */
+    double e_lower;       /* Kato-Temple lower bound E - residual^2 / (eta - E);
+                             [e_lower, E] holds the eigenvalue when eta is a true
+                             lower bound on the next one; NaN if eta <= E         */
 } ed_info;
 
 /* Fill opts with the defaults above. */
 void ed_lanczos_defaults(ed_lanczos_opts *opts);
 
 /* Bytes of DEVICE workspace ed_lanczos_ground (k = 1) or ed_arnoldi_lowest (k)
- * needs with these options.  EINVAL: k < 1 or k > D. */
+ * needs with these options (with max_basis = 0, for the basis planned from the
+ * free device memory; the solver called with that workspace plans the same
+ * basis from its size).  EINVAL: k < 1 or k > D.  ENOMEM: the workspace (with
+ * max_basis = 0: even the smallest usable basis) exceeds the memory available
+ * on the device. */
 ed_status ed_workspace_bytes(ed_ham_t h, const ed_lanczos_opts *opts, int k, size_t *bytes);
 
 /* Lowest eigenvalue of the sector.  v0: DEVICE start vector (D elements, any
@@ -260,6 +274,12 @@ ed_status ed_arnoldi_lowest_more(ed_ham_t h, int k0, int k, const ed_lanczos_opt
                                  void *ws, size_t ws_bytes, double *evals, void *evecs, ed_info *info,
                                  void *stream);
 
+/* Bytes of DEVICE workspace ed_lanczos_tridiag needs for m steps with these
+ * options: m + 1 basis vectors, or 3 with the three-term recurrence
+ * (reorth = 0), which only ever holds the two latest vectors and the new one.
+ * EINVAL: m outside [1, min(D, 1022)]. */
+ed_status ed_tridiag_workspace_bytes(ed_ham_t h, const ed_lanczos_opts *opts, int m, size_t *bytes);
+
 /* Tridiagonal Lanczos coefficients of the Krylov space of v0 (no restart):
  * m steps with the reorthogonalisation of opts->reorth (opts->max_basis and
  * keep are ignored).  alpha[0..m), beta[0..m) HOST outputs with beta[j] the
@@ -267,7 +287,7 @@ ed_status ed_arnoldi_lowest_more(ed_ham_t h, int k0, int k, const ed_lanczos_opt
  * exhausted; then beta[k-1] = 0); *v0_norm2 = ||v0||^2.  These are the
  * continued-fraction coefficients of <v0|(z - H)^-1|v0>, the form in which the
  * impurity Green function of Eq. 3 is evaluated.  ws: DEVICE workspace of at
- * least ed_workspace_bytes(h, opts with max_basis = m, 1).  Synchronous.
+ * least ed_tridiag_workspace_bytes(h, opts, m).  Synchronous.
  * EINVAL: m outside [1, min(D, 1022)], NULL arguments, v0 zero. */
 ed_status ed_lanczos_tridiag(ed_ham_t h, const ed_lanczos_opts *opts, const void *v0, int m, void *ws,
                              size_t ws_bytes, double *alpha, double *beta, int *steps, double *v0_norm2,
@@ -295,7 +315,9 @@ ed_status ed_green_cf(const double *alpha, const double *beta, int k, double nor
 /* Boltzmann weights of Eq. 3 on the host: w[i] = exp(-beta (E[i] - E_min)) / Z
  * for the n computed levels E[0..n) (any sectors), where levels whose share
  * falls below cutoff get w = 0 and Z sums the kept ones, so the kept weights
- * add to 1 and the Green function keeps its total spectral weight.  *kept:
+ * add to 1 and the Green function keeps its total spectral weight.  The levels
+ * at E_min are always kept (a g-fold degenerate lowest level has shares of
+ * 1/g or less, which a cut above that would otherwise remove).  *kept:
  * number of nonzero weights.  The temperature Green function is then
  * sum_i w[i] G_i(z), each G_i the zero-temperature one of level i.  EINVAL:
  * NULL arrays, n < 1, beta not in (0, inf), cutoff not in [0, 1), E non-finite. */
@@ -303,7 +325,10 @@ ed_status ed_boltzmann_weights(const double *E, int n, double beta, double cutof
 
 /* ------------------------------------------------------- sector batching ----
  * All sectors of one impurity problem at once (the paper's solver treats the
- * sectors of the block structure one after another): one restarted Lanczos per
+ * sectors of the block structure one after another, and its closing remarks
+ * of Section 3.2 trace the load imbalance of equal-size splits of the matrix to
+ * rows with unequal work: here each sector's share of every batched kernel is
+ * sized by its own dimension and row work): one restarted Lanczos per
  * sector, all advanced in lockstep; every step is a fixed sequence of batched
  * kernels over all sectors whose step index lives in device memory, captured
  * once in a hipGraph and replayed, with converged sectors masked off on the
@@ -315,6 +340,7 @@ ed_status ed_boltzmann_weights(const double *E, int n, double beta, double cutof
  * stream seed + i).  E0: HOST [nsec] lowest eigenvalue per sector (FP64
  * Rayleigh quotient of the Ritz vector when opts->refine).  info: HOST [nsec]
  * or NULL.  ws: DEVICE workspace of at least ed_batched_workspace_bytes.
+ * max_basis = 0 gives 60 vectors per sector.
  * Synchronous.  ED_ENOCONV if some sector hit max_iter (all E0 still written).
  * The batch restarts explicitly and runs CGS2 (opts->keep is ignored and
  * reorth = 3 runs as 2). */

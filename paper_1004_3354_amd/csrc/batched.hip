@@ -56,6 +56,7 @@ struct BState {      // per-sector scalars, strided by `ms` = m + 2 (or m + 8 fo
 };
 
 static constexpr int kBBS = 256;
+static constexpr int kBatchBasisDefault = 60;  // basis per sector when max_basis = 0
 static int64_t g_last_tile = 0;
 
 // ------------------------------------------------------------------ apply --
@@ -484,7 +485,7 @@ static ed_status run_batched(int nsec, const ed_ham_t *hs, const ed_lanczos_opts
         B.D.push_back(hs[i]->D);
         Dmin = std::min(Dmin, hs[i]->D);
     }
-    B.m = std::max(2, std::min(o.max_basis, 1000));
+    B.m = std::max(2, std::min(o.max_basis == 0 ? kBatchBasisDefault : o.max_basis, 1000));
     B.ms = B.m + 2;
     B.mt = B.m + 8;
     B.mw = 8 + 6 * (B.m + 2) + (B.m + 2) / 2 + 16;
@@ -720,7 +721,7 @@ extern "C" ed_status ed_batched_workspace_bytes(int nsec, const ed_ham_t *hs, co
             B.D.push_back(hs[i]->D);
         }
         B.elem = hs[0]->prec == ED_FP64 ? 8 : 4;
-        B.m = std::max(2, std::min(o.max_basis, 1000));
+        B.m = std::max(2, std::min(o.max_basis == 0 ? kBatchBasisDefault : o.max_basis, 1000));
         B.ms = B.m + 2;
         B.mt = B.m + 8;
         B.mw = 8 + 6 * (B.m + 2) + (B.m + 2) / 2 + 16;

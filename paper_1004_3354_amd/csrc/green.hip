@@ -105,11 +105,13 @@ extern "C" ed_status ed_boltzmann_weights(const double *E, int n, double beta, d
         // states for the cut, second over the kept ones for the normalisation
         double z = 0.0;
         for (int i = 0; i < n; ++i) z += std::exp(-beta * (E[i] - emin));
+        // the lowest levels always stay (with a g-fold degenerate lowest level
+        // each has share <= 1/g, which a cut above 1/g would otherwise remove)
         double zk = 0.0;
         int nk = 0;
         for (int i = 0; i < n; ++i) {
             const double f = std::exp(-beta * (E[i] - emin));
-            w[i] = f / z >= cutoff ? f : 0.0;
+            w[i] = (f / z >= cutoff || E[i] == emin) ? f : 0.0;
             if (w[i] > 0.0) {
                 zk += w[i];
                 ++nk;

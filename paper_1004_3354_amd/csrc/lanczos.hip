@@ -519,6 +519,63 @@ static double tridiag_eig(const std::vector<double> &a, const std::vector<double
     return 0.5 * (lo + hi);
 }
 
+// Last component of the normalised eigenvector of the tridiagonal (a, b) for
+// the eigenvalue theta, by inverse iteration with partial pivoting (three
+// solves of (T - theta I) z = z from z = 1).
+static double tridiag_evec_last(const std::vector<double> &a, const std::vector<double> &b, int m, double theta) {
+    if (m == 1) return 1.0;
+    std::vector<double> z((size_t)m, 1.0), d((size_t)m), dl((size_t)m), du((size_t)m), du2((size_t)m);
+    std::vector<int> piv((size_t)m);
+    const double tiny = 1e-300 + 2.220446049250313e-16 * std::max(std::fabs(theta), 1.0) * 1e-3;
+    for (int rep = 0; rep < 3; ++rep) {
+        for (int i = 0; i < m; ++i) {
+            d[i] = a[i] - theta;
+            dl[i] = du[i] = (i < m - 1) ? b[i] : 0.0;
+            du2[i] = 0.0;
+        }
+        for (int i = 0; i < m - 1; ++i) {
+            if (std::fabs(d[i]) >= std::fabs(dl[i])) {
+                if (d[i] == 0.0) d[i] = tiny;
+                const double f = dl[i] / d[i];
+                dl[i] = f;
+                d[i + 1] -= f * du[i];
+                piv[i] = 0;
+            } else {
+                const double f = d[i] / dl[i];
+                d[i] = dl[i];
+                dl[i] = f;
+                const double t = du[i];
+                du[i] = d[i + 1];
+                d[i + 1] = t - f * d[i + 1];
+                if (i < m - 2) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = -f * du[i + 1];
+                }
+                piv[i] = 1;
+            }
+        }
+        if (d[m - 1] == 0.0) d[m - 1] = tiny;
+        for (int i = 0; i < m - 1; ++i) {
+            if (piv[i] == 0) {
+                z[i + 1] -= dl[i] * z[i];
+            } else {
+                const double t = z[i];
+                z[i] = z[i + 1];
+                z[i + 1] = t - dl[i] * z[i];
+            }
+        }
+        z[m - 1] /= d[m - 1];
+        z[m - 2] = (z[m - 2] - du[m - 2] * z[m - 1]) / d[m - 2];
+        for (int i = m - 3; i >= 0; --i) z[i] = (z[i] - du[i] * z[i + 1] - du2[i] * z[i + 2]) / d[i];
+        double nn = 0.0;
+        for (int i = 0; i < m; ++i) nn += z[i] * z[i];
+        nn = std::sqrt(nn);
+        if (!(nn > 0.0) || !std::isfinite(nn)) return std::nan("");
+        for (int i = 0; i < m; ++i) z[i] /= nn;
+    }
+    return z[m - 1];
+}
+
 // Shifted QR steps on the dense copy of T; returns T+ (dense) and Q (m x m,
 // row-major).  Rotation G_i acts on coordinates (i, i+1).
 static void ir_shift(std::vector<double> &T, std::vector<double> &Q, int m, const std::vector<double> &shifts) {
@@ -558,9 +615,11 @@ static void ir_shift(std::vector<double> &T, std::vector<double> &Q, int m, cons
     }
 }
 
+static constexpr int kAutoBasisMax = 120;  // largest planned basis (max_basis = 0)
+
 static void fill_defaults(ed_lanczos_opts &o) {
     o.max_iter = 600;
-    o.max_basis = 120;
+    o.max_basis = 0;
     o.tol = 1e-10;
     o.reorth = 2;
     o.check_every = 4;
@@ -573,7 +632,8 @@ static ed_lanczos_opts effective(const ed_lanczos_opts *opts, int64_t D) {
     fill_defaults(o);
     if (opts) o = *opts;
     if (o.max_iter <= 0) o.max_iter = 600;
-    if (o.max_basis <= 1) o.max_basis = 120;
+    if (o.max_basis < 0) o.max_basis = 0;      // 0: planned from the memory available
+    if (o.max_basis == 1) o.max_basis = 2;
     if (o.max_basis > 1000) o.max_basis = 1000;
     if ((int64_t)o.max_basis > D) o.max_basis = (int)std::max<int64_t>(D, 1);
     if (!(o.tol > 0.0)) o.tol = 1e-10;
@@ -581,19 +641,23 @@ static ed_lanczos_opts effective(const ed_lanczos_opts *opts, int64_t D) {
     if (o.check_every <= 0) o.check_every = 4;
     if (o.keep < 0 || o.max_basis > kIRMaxIn - 1) o.keep = 0;
     if (o.keep > kIRMaxOut - 1) o.keep = kIRMaxOut - 1;
-    if (o.keep >= o.max_basis) o.keep = o.max_basis - 1;
+    if (o.max_basis > 0 && o.keep >= o.max_basis) o.keep = o.max_basis - 1;
     return o;
 }
 
 // Lay out the workspace; with base == nullptr only the size is computed.
-static size_t layout(Work &w, char *base, int64_t D, size_t elem, int m, int kmax, bool locked_in_ws) {
+// nslots: basis slots of D elements (m + 1, or 3 for the three-term
+// recurrence of ed_lanczos_tridiag, which only ever holds S_{j-1}, S_j, S_{j+1}).
+static size_t layout(Work &w, char *base, int64_t D, size_t elem, int m, int kmax, bool locked_in_ws,
+                     int nslots = -1) {
     Carve c{base, 0, 0};
     w.m = m;
     w.kmax = kmax;
     w.elem = elem;
     w.nblk = reduce_blocks(D);
-    w.slots.assign(m + 1, nullptr);
-    for (int i = 0; i <= m; ++i) w.slots[i] = c.take((size_t)D * elem);
+    if (nslots < 0) nslots = m + 1;
+    w.slots.assign(nslots, nullptr);
+    for (int i = 0; i < nslots; ++i) w.slots[i] = c.take((size_t)D * elem);
     w.locked.assign(kmax, nullptr);
     if (locked_in_ws)
         for (int i = 0; i < kmax; ++i) w.locked[i] = c.take((size_t)D * elem);
@@ -788,7 +852,10 @@ struct Solver {
     // and ||v0||^2 in *v0n2.  Ground-state style storage: locked vectors none.
     int tridiag(const void *v0, int m, double *alpha_h, double *beta_h, double *v0n2) {
         ED_HIP(hipMemcpyAsync(w.slots[0], v0, (size_t)h->D * w.elem, hipMemcpyDeviceToDevice, s));
-        std::vector<void *> kr(w.slots.begin(), w.slots.end());
+        // basis index i lives in slot i (full reorthogonalisation) or i mod 3
+        // (three-term recurrence: only S_{j-1}, S_j and the new vector are read)
+        std::vector<void *> kr((size_t)m + 1);
+        for (int i = 0; i <= m; ++i) kr[i] = w.slots[(size_t)i % w.slots.size()];
         upload_pointers(kr);
         *v0n2 = norm2_sync(0, kr[0]);
         prepare_start(kr[0]);
@@ -832,6 +899,32 @@ struct Solver {
             }
         }
         return m;
+    }
+
+    // Two-sided interval for the eigenvalue just found.  The Rayleigh quotient
+    // rq is an upper bound (variational).  The Kato-Temple inequality gives
+    // lambda >= rq - r^2 / (eta - rq) for any eta with rq < eta <= the next
+    // eigenvalue of the (deflated) operator; eta is taken as the second Ritz
+    // value of the last cycle's tridiagonal matrix minus its residual bound
+    // |beta_m s_m|, which is a lower bound on the next eigenvalue as long as
+    // the iteration has not missed one between the two Ritz values.  NaN when
+    // there is no second Ritz value or the gap is not resolved.
+    void kato_temple(int m, double rq, double r, ed_info *inf) {
+        inf->gap_lower = std::nan("");
+        inf->e_lower = std::nan("");
+        if (m < 2) return;
+        std::vector<double> al((size_t)m), be((size_t)m);
+        ED_HIP(hipMemcpyAsync(al.data(), w.alpha, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+        ED_HIP(hipMemcpyAsync(be.data(), w.beta, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+        ED_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < m; ++i)
+            if (!std::isfinite(al[i]) || !std::isfinite(be[i])) return;
+        const double t2 = tridiag_eig(al, be, m, 1);
+        const double z = tridiag_evec_last(al, be, m, t2);
+        if (!std::isfinite(z)) return;
+        const double eta = t2 - std::fabs(be[m - 1] * z);
+        inf->gap_lower = eta;
+        if (eta > rq && std::isfinite(r)) inf->e_lower = rq - r * r / (eta - rq);
     }
 
     ed_status run(const void *v0, void *out, double *E, ed_info *info, int64_t fresh = -1) {
@@ -981,6 +1074,7 @@ struct Solver {
             *E = theta;
         }
         ED_HIP(hipStreamSynchronize(s));
+        kato_temple(jlast, rq, rr, &inf);
         if (info) *info = inf;
         return converged ? ED_OK : ED_ENOCONV;
     }
@@ -989,6 +1083,58 @@ struct Solver {
 static size_t ws_needed(const ed_ham_s *h, const ed_lanczos_opts &o, int k, bool locked_in_ws) {
     Work w;
     return layout(w, nullptr, h->D, h->prec == ED_FP64 ? 8 : 4, o.max_basis, k, locked_in_ws);
+}
+
+// Smallest usable basis: two vectors, or the kept block of an implicit restart
+// plus two.
+static int min_basis(const ed_ham_s *h, const ed_lanczos_opts &o) {
+    return (int)std::min<int64_t>(std::max(2, o.keep + 2), std::max<int64_t>(h->D, 1));
+}
+
+// Memory planner (max_basis = 0): the largest basis, at most kAutoBasisMax
+// vectors (and the per-kernel pointer limit), whose workspace fits `budget`
+// bytes.  ENOMEM when even the smallest usable basis does not fit.
+static int plan_basis(const ed_ham_s *h, ed_lanczos_opts o, int k, bool locked_in_ws, size_t budget) {
+    int lo = min_basis(h, o);
+    int hi = (int)std::min<int64_t>(std::min(kAutoBasisMax, kMaxVec - 2 - k), std::max<int64_t>(h->D, 1));
+    if (hi < lo) hi = lo;
+    o.max_basis = lo;
+    if (ws_needed(h, o, k, locked_in_ws) > budget)
+        fail(ED_ENOMEM, "no Lanczos workspace fits: %d basis vectors of %lld elements need %zu bytes, %zu available",
+             lo, (long long)h->D, ws_needed(h, o, k, locked_in_ws), budget);
+    while (lo < hi) {  // largest m with ws_needed(m) <= budget
+        const int mid = (lo + hi + 1) / 2;
+        o.max_basis = mid;
+        if (ws_needed(h, o, k, locked_in_ws) <= budget) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Device memory a new workspace may take: what the runtime reports free, less
+// a reserve for the library's own tables and the caller's other buffers.
+static size_t device_budget() {
+    size_t fr = 0, tot = 0;
+    ED_HIP(hipMemGetInfo(&fr, &tot));
+    const size_t reserve = std::max<size_t>((size_t)1 << 30, tot / 50);
+    return fr > reserve ? fr - reserve : 0;
+}
+
+// Options with the basis size resolved: max_basis = 0 is planned against
+// `budget` (the free device memory for a size query, the given workspace for a
+// solve); an explicit basis is capped by the pointer limit of the kernels.
+static ed_lanczos_opts resolve(const ed_ham_s *h, const ed_lanczos_opts *opts, int k, bool locked_in_ws,
+                               size_t budget) {
+    ed_lanczos_opts o = effective(opts, h->D);
+    if (o.max_basis == 0) o.max_basis = plan_basis(h, o, k, locked_in_ws, budget);
+    if (o.max_basis > kMaxVec - 2 - k) o.max_basis = kMaxVec - 2 - k;
+    if (o.keep >= o.max_basis) o.keep = o.max_basis - 1;
+    return o;
+}
+
+static size_t tridiag_ws_needed(const ed_ham_s *h, const ed_lanczos_opts &o, int m) {
+    Work w;
+    return layout(w, nullptr, h->D, h->prec == ED_FP64 ? 8 : 4, m, 1, true, o.reorth == 0 ? std::min(3, m + 1) : m + 1);
 }
 
 }  // namespace ed
@@ -1004,9 +1150,24 @@ extern "C" ed_status ed_workspace_bytes(ed_ham_t h, const ed_lanczos_opts *opts,
         if (!h || !bytes) fail(ED_EINVAL, "ed_workspace_bytes: NULL argument");
         if (k < 1 || (int64_t)k > h->D) fail(ED_EINVAL, "ed_workspace_bytes: k=%d outside [1, D=%lld]", k, (long long)h->D);
         if (k > 200) fail(ED_EINVAL, "ed_workspace_bytes: k=%d above 200", k);
-        ed_lanczos_opts o = effective(opts, h->D);
-        if (o.max_basis > kMaxVec - 2 - k) o.max_basis = kMaxVec - 2 - k;
+        DeviceGuard g(h->device);
+        const size_t budget = device_budget();
+        const ed_lanczos_opts o = resolve(h, opts, k, true, budget);
         *bytes = ws_needed(h, o, k, true);
+        if (*bytes > budget)
+            fail(ED_ENOMEM, "workspace of %zu bytes (%d basis vectors of %lld elements) exceeds the %zu bytes "
+                 "available on the device; use a smaller max_basis or max_basis = 0 to plan it",
+                 *bytes, o.max_basis, (long long)h->D, budget);
+    });
+}
+
+extern "C" ed_status ed_tridiag_workspace_bytes(ed_ham_t h, const ed_lanczos_opts *opts, int m, size_t *bytes) {
+    return guard([&] {
+        if (!h || !bytes) fail(ED_EINVAL, "ed_tridiag_workspace_bytes: NULL argument");
+        if (m < 1 || (int64_t)m > h->D || m > kMaxVec - 2)
+            fail(ED_EINVAL, "m=%d outside [1, min(D=%lld, %d)]", m, (long long)h->D, kMaxVec - 2);
+        const ed_lanczos_opts o = effective(opts, h->D);
+        *bytes = tridiag_ws_needed(h, o, m);
     });
 }
 
@@ -1026,11 +1187,10 @@ static ed_status solve(ed_ham_t h, int k, const ed_lanczos_opts *opts, const voi
         Solver sv;
         sv.h = h;
         sv.s = (hipStream_t)stream;
-        sv.o = effective(opts, h->D);
         // eigenpair e runs cycles of at most D - e steps (the deflated space)
         if (k > 200) fail(ED_EINVAL, "k=%d above 200", k);
-        if (sv.o.max_basis > kMaxVec - 2 - k) sv.o.max_basis = kMaxVec - 2 - k;
         const bool locked_in_ws = (evecs == nullptr);
+        sv.o = resolve(h, opts, k, locked_in_ws, ws_bytes);
         const size_t need = ws_needed(h, sv.o, k, locked_in_ws);
         if (ws_bytes < need) fail(ED_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
         layout(sv.w, (char *)ws, h->D, h->prec == ED_FP64 ? 8 : 4, sv.o.max_basis, k, locked_in_ws);
@@ -1098,9 +1258,10 @@ extern "C" ed_status ed_lanczos_tridiag(ed_ham_t h, const ed_lanczos_opts *opts,
         sv.o = effective(opts, h->D);
         sv.o.max_basis = m;
         sv.o.keep = 0;
-        const size_t need = ws_needed(h, sv.o, 1, true);
+        const size_t need = tridiag_ws_needed(h, sv.o, m);
         if (ws_bytes < need) fail(ED_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
-        layout(sv.w, (char *)ws, h->D, h->prec == ED_FP64 ? 8 : 4, m, 1, true);
+        layout(sv.w, (char *)ws, h->D, h->prec == ED_FP64 ? 8 : 4, m, 1, true,
+               sv.o.reorth == 0 ? std::min(3, m + 1) : m + 1);
         *steps = sv.tridiag(v0, m, alpha, beta, v0_norm2);
     });
 }

@@ -56,7 +56,7 @@ class ed_lanczos_opts(ctypes.Structure):
 class ed_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("basis_used", ctypes.c_int32), ("residual", ctypes.c_double), ("ritz", ctypes.c_double),
-                ("rq_fp64", ctypes.c_double)]
+                ("rq_fp64", ctypes.c_double), ("gap_lower", ctypes.c_double), ("e_lower", ctypes.c_double)]
 
     def as_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -98,6 +98,8 @@ _sig("ed_arnoldi_lowest", ctypes.c_int, [_p, ctypes.c_int, ctypes.POINTER(ed_lan
                                          ctypes.c_size_t, _p, _p, _p, _p])
 _sig("ed_arnoldi_lowest_more", ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ed_lanczos_opts), _p,
                                               _p, ctypes.c_size_t, _p, _p, _p, _p])
+_sig("ed_tridiag_workspace_bytes", ctypes.c_int, [_p, ctypes.POINTER(ed_lanczos_opts), ctypes.c_int,
+                                                  ctypes.POINTER(ctypes.c_size_t)])
 _sig("ed_lanczos_tridiag", ctypes.c_int, [_p, ctypes.POINTER(ed_lanczos_opts), _p, ctypes.c_int, _p, ctypes.c_size_t,
                                           _p, _p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), _p])
 _sig("ed_apply_ladder", ctypes.c_int, [_p, _p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _p, _p, _p])
@@ -249,6 +251,12 @@ class Hamiltonian:
         _check(_lib.ed_workspace_bytes(self._h, ctypes.byref(o), k, ctypes.byref(n)))
         return n.value
 
+    def tridiag_workspace_bytes(self, m: int, opts=None) -> int:
+        o = opts if opts is not None else options()
+        n = ctypes.c_size_t()
+        _check(_lib.ed_tridiag_workspace_bytes(self._h, ctypes.byref(o), m, ctypes.byref(n)))
+        return n.value
+
     def lanczos_ground(self, v0, opts=None, ws=None, psi=None, stream=None, allow_noconv=False):
         import torch
         o = opts if opts is not None else options()
@@ -298,9 +306,7 @@ class Hamiltonian:
         """(alpha, beta, ||v0||^2): k <= m tridiagonal Lanczos coefficients from v0."""
         import torch
         o = options() if opts is None else opts
-        o = ed_lanczos_opts.from_buffer_copy(o)
-        o.max_basis = m
-        nb = self.workspace_bytes(o, 1)
+        nb = self.tridiag_workspace_bytes(m, o)
         if ws is None:
             ws = torch.empty(nb, dtype=torch.uint8, device=v0.device)
         a = np.zeros(m, dtype=np.float64)
@@ -410,7 +416,8 @@ def green_function(H0: "Hamiltonian", e0: float, psi0, Hp: "Hamiltonian", Hm: "H
     fractions: lost orthogonality duplicates converged poles but leaves the
     moments the fraction matches intact, at a fraction of the cost of full
     reorthogonalisation.  ws: optional DEVICE workspace for the Lanczos runs, large
-    enough for both neighbouring sectors.  Returns (G or g, details)."""
+    enough for both neighbouring sectors (tridiag_workspace_bytes).  Returns
+    (G or g, details)."""
     import torch
     z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
     if g is None:
@@ -554,14 +561,27 @@ def green_thermal(params: Dict, ns: int, sectors: Sequence[Tuple[int, int]], spi
         edge = sorted({sec for (sec, i, e), wi in zip(levels, w) if wi > 0.0 and i == k - 1 and k < ham(sec).D})
     else:   # every sector's levels up to the K-th are in; weight left on the K-th itself
         edge = [] if w[-1] == 0.0 or len(levels) < K else ["K-th level above the cut"]
-    for (sec, i, e), wi in zip(levels, w):
-        if wi == 0.0:
-            continue
-        H0 = ham(sec)
-        psi = vecs[sec][i * H0.D:(i + 1) * H0.D]
+        # sectors stopped at kmax before their levels passed the K-th may hold more
+        edge += [secs[s] for s in ldet["capped"]]
+    kept_lv = [((sec, i, e), wi) for (sec, i, e), wi in zip(levels, w) if wi != 0.0]
+    gopts = opts if opts is not None else options(reorth=0)
+
+    def nbrs(sec):
         nu, nd = sec
         up = (nu + 1, nd) if spin == 0 else (nu, nd + 1)
         dn = (nu - 1, nd) if spin == 0 else (nu, nd - 1)
-        green_function(H0, e, psi, ham(up), ham(dn), spin, site, z, m=m, opts=opts, weight=wi, g=g)
+        return ham(up), ham(dn)
+    # one workspace for every level's two Lanczos runs (the largest neighbour)
+    nbytes = 1
+    for (sec, _, _), _ in kept_lv:
+        for Hx in nbrs(sec):
+            if Hx is not None:
+                nbytes = max(nbytes, Hx.tridiag_workspace_bytes(min(m, Hx.D), gopts))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    for (sec, i, e), wi in kept_lv:
+        H0 = ham(sec)
+        psi = vecs[sec][i * H0.D:(i + 1) * H0.D]
+        Hp, Hm = nbrs(sec)
+        green_function(H0, e, psi, Hp, Hm, spin, site, z, m=m, opts=gopts, weight=wi, g=g, ws=ws)
     details = {"levels": [(sec, i, e, float(wi)) for (sec, i, e), wi in zip(levels, w)], "kept": kept, "edge": edge}
     return g, details

@@ -50,6 +50,7 @@ def test_invalid_arguments_rejected(lib):
 def test_default_options(lib):
     from paper_1004_3354_amd import ed
     o = ed.options()
-    assert o.max_iter > 0 and o.max_basis > 1 and o.tol > 0 and o.reorth == 2
+    # max_basis = 0: the basis is planned from the device memory (or the workspace)
+    assert o.max_iter > 0 and o.max_basis == 0 and o.tol > 0 and o.reorth == 2
     assert ed.variant_count() >= 4
     assert all(ed.variant_name(v) for v in range(ed.variant_count()))

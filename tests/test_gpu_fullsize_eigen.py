@@ -1,0 +1,137 @@
+"""Eigenvalues at the full benchmark sizes, where the oracle's stored CSR
+matrix does not fit a host.
+
+4 x 4 periodic Hubbard model (Eq. 1, t = 1), half filling, sector (8, 8),
+D = 12870^2 = 165,636,900 (the N_s = 16 sector of Table 1):
+  * U = 0: E0 = -24 exactly.  The one-body levels of the 4 x 4 torus are
+    -2(cos kx + cos ky): -4 once, -2 four times, 0 six times, ...; eight
+    electrons per spin fill -4, the four -2 and three of the zero levels,
+    so E0 = 2 (-4 - 8) = -24.  This pins the full-size Lanczos (apply,
+    reorthogonalisation, tridiagonal solve, refinement) with no matrix at all.
+  * U = 4: E0 against the oracle's value (three-term Lanczos on its
+    matrix-free literal rows, tests/golden/oracle_e0.json "cfg1"), inside the
+    Kato-Temple interval of the returned vector; the 4 lowest eigenvalues with
+    multiplicity from the FP64 and the FP32-mixed path agree with each other.
+N_s = 18 three-orbital impurity, sector (9, 9), D = 48620^2: the 3 lowest
+eigenvalues in FP32-mixed with a capped basis (9.5 GB per vector), each with
+its FP64 residual and Kato-Temple interval.
+
+Tolerances: 1e-10 (FP64) and 1e-6 (FP32-mixed) relative to max(|E|, 1), the
+required accuracy of each path.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import gpu_ed
+from paper_1004_3354_amd import models, workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_e0.json")
+TOL = {0: 1e-10, 1: 1e-6}
+
+
+def _hubbard(U, prec):
+    ed = gpu_ed()
+    b = ed.Basis(16, 8, 8)
+    H = ed.Hamiltonian(models.hubbard_params(4, 4, 1.0, U), b, prec)
+    return b, H
+
+
+def _v0(H, prec, seed):
+    ed = gpu_ed()
+    v0 = torch.empty(H.D, dtype=torch.float64 if prec == 0 else torch.float32, device="cuda")
+    ed.fill_random(v0, seed, 1)
+    return v0
+
+
+def _golden(key, sec):
+    if not os.path.exists(GOLD):
+        return None
+    e = json.load(open(GOLD))["entries"].get(key)
+    return None if e is None else e["sectors"][sec]["evals"]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_hubbard4x4_u0_full_size_pin(prec):
+    ed = gpu_ed()
+    b, H = _hubbard(0.0, prec)
+    assert H.D == 165636900
+    v0 = _v0(H, prec, wl.start_vector_seed(1))
+    # the default options plan the basis from the free device memory
+    opts = ed.options(tol=1e-10 if prec == 0 else 1e-7, reorth=3, keep=8, max_basis=24 if prec == 0 else 0)
+    E, info = H.lanczos_ground(v0, opts)
+    assert info["converged"] == 1
+    assert abs(E - (-24.0)) <= TOL[prec] * 24.0, (E, info)
+    assert info["e_lower"] <= -24.0 + TOL[prec] * 24.0 or not np.isfinite(info["e_lower"])
+
+
+@pytest.fixture(scope="module")
+def hubbard_u4_lowest():
+    """The 4 lowest levels of the 4 x 4 U = 4 sector in both precisions."""
+    ed = gpu_ed()
+    out = {}
+    for prec in (0, 1):
+        b, H = _hubbard(4.0, prec)
+        v0 = _v0(H, prec, wl.start_vector_seed(1))
+        opts = ed.options(tol=1e-10 if prec == 0 else 1e-7, reorth=2, keep=8, max_basis=24, max_iter=4000)
+        ev, infos = H.lowest(4, v0, opts)
+        print("4x4 U=4 %s: %s" % ("fp64" if prec == 0 else "fp32", ev), flush=True)
+        out[prec] = (ev, infos)
+        del H, b, v0
+        torch.cuda.empty_cache()
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_hubbard4x4_u4_e0_vs_oracle(hubbard_u4_lowest, prec):
+    ev, infos = hubbard_u4_lowest[prec]
+    ref = _golden("cfg1", "8,8")
+    if ref is None:
+        pytest.skip("oracle value not written yet (python tests/golden/make_golden.py 1)")
+    e0 = ref[0]
+    assert abs(ev[0] - e0) <= TOL[prec] * max(1.0, abs(e0)), (ev[0], e0)
+    # the oracle value lies in the Kato-Temple interval [e_lower, E] (up to the tolerance)
+    lo = infos[0]["e_lower"]
+    assert np.isfinite(lo) and lo - TOL[prec] * abs(e0) <= e0 <= ev[0] + TOL[prec] * abs(e0), (lo, e0, ev[0])
+
+
+def test_hubbard4x4_u4_lowest4_fp32_vs_fp64(hubbard_u4_lowest):
+    e64, i64 = hubbard_u4_lowest[0]
+    e32, i32 = hubbard_u4_lowest[1]
+    assert np.all(np.diff(e64) >= -1e-9) and np.all(np.diff(e32) >= -1e-6)
+    scale = max(1.0, float(np.max(np.abs(e64))))
+    assert np.max(np.abs(e64 - e32)) <= TOL[1] * scale, (e64, e32)
+    for inf in i64:
+        assert inf["converged"] == 1 and inf["residual"] <= 1e-7 * scale, inf
+    for inf in i32:
+        assert inf["converged"] == 1 and inf["residual"] <= 1e-4 * scale, inf
+
+
+def test_ns18_lowest3_fp32():
+    """N_s = 18, sector (9, 9): three lowest levels with a capped FP32 basis
+    (3 locked vectors + 16 basis vectors of 9.5 GB)."""
+    ed = gpu_ed()
+    phys, sectors = wl.config(4)
+    (nu, nd), = sectors
+    b = ed.Basis(18, nu, nd)
+    H = ed.Hamiltonian(models.params_from_model(phys), b, ed.ED_FP32)
+    v0 = _v0(H, 1, wl.start_vector_seed(4))
+    opts = ed.options(tol=1e-7, reorth=3, keep=8, max_basis=16, max_iter=3000)
+    evecs = torch.empty((3, H.D), dtype=torch.float32, device="cuda")
+    ev, infos = H.lowest(1, v0, opts, evecs=evecs[:1])
+    print("N_s=18 level 0: %.12f (%d steps)" % (ev[0], infos[0]["iters"]), flush=True)
+    for k in (2, 3):     # one level at a time on top of the converged ones
+        ev, more = H.lowest_more(k - 1, k, ev, v0, evecs[:k], opts)
+        infos = infos + more
+        print("N_s=18 level %d: %.12f (%d steps)" % (k - 1, ev[k - 1], more[0]["iters"]), flush=True)
+    assert np.all(np.diff(ev) >= -1e-6 * abs(ev[0]))
+    for e, inf in zip(ev, infos):
+        assert inf["converged"] == 1, inf
+        # FP64 residual of the FP32-stored vector, relative to |E|
+        assert inf["residual"] <= 1e-4 * abs(e), inf
+        if np.isfinite(inf["e_lower"]):
+            assert inf["e_lower"] <= e

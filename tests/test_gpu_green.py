@@ -4,10 +4,10 @@ Ladder operators move and sign-flip elements only, so they are compared bit
 for bit with the oracle's literal Jordan-Wigner application, for both spins,
 c and c+, and both precisions.  The Green function (GPU ground state, GPU
 ladder, GPU Lanczos coefficients, continued fraction) is compared with the
-oracle's dense Lehmann sum on small non-degenerate sectors.  At the full
-Ns = 15 size the properties that hold at any size are checked instead: c c+ +
-c+ c = 1 element by element, the spectral weights summing to 1, causality and
-the 1/z tail.
+oracle's dense Lehmann sum on small non-degenerate sectors.  At full size
+(the N_s = 15 three-orbital impurity and the 4 x 4 Hubbard model) the
+properties that hold at any size are checked instead: c c+ + c+ c = 1 element
+by element, the spectral weights summing to 1, causality and the 1/z tail.
 
 The continued fractions run to m = 500 levels (or the whole sector): at
 z = w + 0.15i the truncation error of the 200-level fraction of the Ns = 8
@@ -192,17 +192,18 @@ def test_green_function_empty_side():
     assert np.max(np.abs(g - ref)) / np.max(np.abs(ref)) <= TOL[0]
 
 
-def _full_size_ladder_identity(prec):
-    """c c+ x + c+ c x = x at Ns = 15, sector (7, 7), element by element and exactly."""
+def _full_size_ladder_identity(phys, prec):
+    """c c+ x + c+ c x = x at sector (7, 7) of a full-size model, element by
+    element and exactly, for spin up on three sites."""
     ed = gpu_ed()
-    phys, _ = wl.config(1)
+    ns = int(phys["Ns"])
     _, H0 = build(phys, 7, 7, prec)
     _, Hp = build(phys, 8, 7, prec)
     _, Hm = build(phys, 6, 7, prec)
     dt = torch.float64 if prec == 0 else torch.float32
     x = torch.empty(H0.D, dtype=dt, device=DEV)
     ed.fill_random(x, 77, 1)
-    for site in (0, 7, 14):
+    for site in (0, ns // 2, ns - 1):
         a = torch.empty(Hp.D, dtype=dt, device=DEV)
         b = torch.empty(Hm.D, dtype=dt, device=DEV)
         r1 = torch.empty_like(x)
@@ -215,13 +216,11 @@ def _full_size_ladder_identity(prec):
         assert torch.equal(r1 + r2, x), site
         # exactly one of the two paths carries each element
         assert int(((r1 != 0) & (r2 != 0)).sum()) == 0
+        del a, b, r1, r2
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
-def test_full_size_ns15_properties(prec):
-    _full_size_ladder_identity(prec)
-    ed = gpu_ed()
-    phys, _ = wl.config(1)
+def _full_size_properties(phys, prec):
+    _full_size_ladder_identity(phys, prec)
     z = np.concatenate([ZM, [1e4j]])
     (g, info), e0 = _green_gpu(phys, (7, 7), 0, 0, prec, z, m=100, tol64=1e-11, reorth=3)
     wsum = info["particle"]["weight"] + info["hole"]["weight"]
@@ -231,6 +230,24 @@ def test_full_size_ns15_properties(prec):
     # the spectral sum rule only fixes the total, the split is the filling of the orbital
     assert 0.0 < info["particle"]["weight"] < 1.0
     assert info["particle"]["steps"] >= 50 and info["hole"]["steps"] >= 50
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_full_size_ns15_properties(prec):
+    """The three-orbital impurity of the N_s = 15 workload (3 orbitals + 12 bath
+    levels), ground sector (7, 7), its neighbours (8, 7) and (6, 7)."""
+    phys, sectors = wl.config(2)
+    assert int(phys["Ns"]) == 15 and sectors == [(7, 7)]
+    _full_size_properties(phys, prec)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_full_size_hubbard4x4_properties(prec):
+    """The 4 x 4 periodic Hubbard model (N_s = 16) one electron below half
+    filling per spin, sector (7, 7) (D = 11440^2), and its neighbours."""
+    phys, _ = wl.config(1)
+    assert int(phys["Ns"]) == 16
+    _full_size_properties(phys, prec)
 
 
 # ------------------------------------------------ finite temperature (Eq. 3) --
@@ -246,6 +263,11 @@ def test_boltzmann_weights():
     f = np.exp(-2.0 * (E - E.min()))
     f[4] = 0.0
     assert kept == 4 and w[4] == 0.0 and np.allclose(w, f / f.sum(), rtol=1e-15, atol=0)
+    # a three-fold degenerate lowest level with a cut above 1/3: the lowest
+    # levels stay (each 1/3), the rest is cut
+    w, kept = ed.boltzmann_weights(np.array([-1.0, 5.0, -1.0, -1.0]), 10.0, cutoff=0.5)
+    assert kept == 3 and np.all(np.isfinite(w)) and w[1] == 0.0
+    assert np.allclose(w[[0, 2, 3]], 1.0 / 3.0, rtol=1e-15, atol=0)
     for args in ((E, 0.0), (E, np.inf), (E, 1.0, 1.0), ([], 1.0), ([np.nan], 1.0)):
         with pytest.raises(ed.EDError):
             ed.boltzmann_weights(*args)
