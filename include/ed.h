@@ -183,7 +183,41 @@ ed_status ed_rayleigh(ed_ham_t h, const void *x, double *rq, double *resid, void
 ed_status ed_fill_random(void *x, int64_t n, uint64_t seed, int dist, int precision,
                          void *stream);
 
+/* Frees h and the grouped twin it owns; a no-op on the twin itself. */
 void ed_ham_free(ed_ham_t h);
+
+/* ------------------------------------------------------- grouped order ------
+ * The paper's solver distributes H by rows; here the vector stays on one GPU
+ * and the work is tiled so that the data a tile reads stays in the caches.
+ * When the one-spin move graph of either spin (hops and same-spin two-body
+ * moves) has several connected components -- the multi-orbital impurity of
+ * Section 4 and the Anderson impurity of Eq. 2 with their bath levels attached
+ * to one orbital each -- ed_ham_create also builds the same operator in a
+ * grouped basis order: the states of each spin ordered by component
+ * (components by their lowest rank), by rank within a component.  Every hop
+ * then stays inside an (up component x down component) tile of the vector.
+ * The solvers iterate in that order by default (ed_lanczos_opts.layout) and
+ * convert their vectors at the boundary; these calls expose it.
+ *
+ * ed_ham_grouped: *grouped = the twin handle (owned by h: do not free it; it
+ * lives as long as h), h itself if h is a twin, or NULL when both move graphs
+ * are connected (then the rank order is the only one).  The twin accepts every
+ * call a handle does (ed_apply_H, the solvers, ...), with vectors in its order:
+ * element (p_up, p_dn) at p_up * D_dn + p_dn, p the position in the grouped
+ * order of that spin. */
+ed_status ed_ham_grouped(ed_ham_t h, ed_ham_t *grouped);
+
+/* rank_of_position[p] (HOST, D_sigma entries) = combinatorial rank of the state
+ * at position p of the grouped order of a twin handle g.  EINVAL: g not a twin,
+ * spin not 0/1, NULL. */
+ed_status ed_grouped_order(ed_ham_t g, int spin, int32_t *rank_of_position);
+
+/* DEVICE vectors of D elements of the handle's precision: y = x converted from
+ * rank order to the grouped order (ed_to_grouped) or back (ed_from_grouped).
+ * h: a handle with a twin, or the twin.  Asynchronous on stream.  EINVAL: no
+ * grouped order, NULL or aliasing vectors. */
+ed_status ed_to_grouped(ed_ham_t h, const void *x, void *y, void *stream);
+ed_status ed_from_grouped(ed_ham_t h, const void *x, void *y, void *stream);
 
 /* ------------------------------------------------------------ eigensolvers --
  * Lanczos iteration (Section 3) with full reorthogonalisation against every
@@ -210,6 +244,9 @@ typedef struct {
                              matrix, which stays tridiagonal), for the ground state
                              and for each eigenpair of ed_arnoldi_lowest on its
                              deflated space; k <= 16, k < max_basis <= 256           */
+    int32_t layout;       /* 0 (default): iterate in the grouped basis order when the
+                             Hamiltonian has one (ed_ham_grouped), converting the
+                             start vector and the returned vectors; 1: rank order    */
 } ed_lanczos_opts;
 
 typedef struct {
@@ -234,9 +271,9 @@ void ed_lanczos_defaults(ed_lanczos_opts *opts);
 /* Bytes of DEVICE workspace ed_lanczos_ground (k = 1) or ed_arnoldi_lowest (k)
  * needs with these options (with max_basis = 0, for the basis planned from the
  * free device memory; the solver called with that workspace plans the same
- * basis from its size).  EINVAL: k < 1 or k > D.  ENOMEM: the workspace (with
- * max_basis = 0: even the smallest usable basis) exceeds the memory available
- * on the device. */
+ * basis from its size).  EINVAL: k < 1 or k > D.  ENOMEM: with max_basis = 0,
+ * even the smallest usable basis exceeds the free device memory; with an
+ * explicit max_basis, the workspace exceeds the device's capacity. */
 ed_status ed_workspace_bytes(ed_ham_t h, const ed_lanczos_opts *opts, int k, size_t *bytes);
 
 /* Lowest eigenvalue of the sector.  v0: DEVICE start vector (D elements, any

@@ -491,7 +491,11 @@ __device__ __forceinline__ TA cross_term_l(const ApplyArgs<TX, TA> &a, const TA 
     return c;
 }
 
-template <typename TX, typename TA, int R, int BS, bool UPX, bool NTY>
+// GRP = true: the grouped-order tile schedule (work list; windows are whole
+// down components, so every down hop reads the staged tile; four-fermion
+// partners lie in other tiles and are read from memory; element offsets are
+// 32-bit, D < 2^32).
+template <typename TX, typename TA, int R, int BS, bool UPX, bool NTY, bool GRP = false>
 __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
     using RVt = typename RV<TX, R>::t;
     using V = typename V4<TX>::t;
@@ -511,15 +515,25 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
         for (int k = threadIdx.x; k < (1 << (2 * a.koff)); k += BS) xtl[k] = a.xtab[k];
 
     const int64_t ddn = a.ddn;
-    const int nwin = a.nwin;
-    const int64_t G = (a.dup + R - 1) / R;
-    const int64_t t = xcd_remap(blockIdx.x, G * nwin);
-    const int64_t g = t / nwin;
-    const int wi = (int)(t - g * nwin);
+    int64_t u0;
+    int nr, wi;
+    if (a.items) {  // grouped schedules: tile-major work list
+        const int4 it = a.items[blockIdx.x];
+        if (it.y <= 0) return;  // padding item (the whole workgroup leaves before any barrier)
+        u0 = it.x;
+        nr = it.y;
+        wi = it.z;
+    } else {
+        const int nwin = a.nwin;
+        const int64_t G = (a.dup + R - 1) / R;
+        const int64_t t = xcd_remap(blockIdx.x, G * nwin);
+        const int64_t g = t / nwin;
+        wi = (int)(t - g * nwin);
+        u0 = g * R;
+        nr = (int)((a.dup - u0) < R ? (a.dup - u0) : R);
+    }
     // rank of the row in each slot of the tile (unused slots repeat slot 0)
     int32_t ur[R];
-    const int64_t u0 = g * R;
-    const int nr = (int)((a.dup - u0) < R ? (a.dup - u0) : R);
 #pragma unroll
     for (int r = 0; r < R; ++r) ur[r] = (int32_t)(u0 + (r < nr ? r : 0));
     const int32_t w0 = a.win[wi].x, wl = a.win[wi].y;
@@ -636,7 +650,11 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
                     const int32_t t = (int32_t)(ev[j] & 0xFFFFFu);
                     const TA am = amps[ev[j] >> 20];
                     const int32_t l = t - w0;
-                    if ((uint32_t)l < (uint32_t)wl) {
+                    if constexpr (GRP) {  // the window holds the whole component
+                        const RVt v = *reinterpret_cast<const RVt *>(xs + (uint32_t)l * R);
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[r][j] += am * (TA)rv_get<TX, R>(v, r);
+                    } else if ((uint32_t)l < (uint32_t)wl) {
                         const RVt v = *reinterpret_cast<const RVt *>(xs + (int64_t)l * R);
 #pragma unroll
                         for (int r = 0; r < R; ++r) acc[r][j] += am * (TA)rv_get<TX, R>(v, r);
@@ -648,9 +666,37 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
                 }
             }
         }
-        // four-fermion terms: the rows' lists are ordered by down move, so each
-        // move table entry is loaded once for all rows of the tile
-        if (a.nx) {
+        // four-fermion terms
+        if constexpr (GRP) {
+            // both moves leave the tile's components: partners from memory
+            if (a.nx) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r >= nr) break;
+                    for (int k = 0; k < nxl[r]; ++k) {
+                        const TX *src = a.x + (uint32_t)x_src[r][k] * (uint32_t)ddn;
+                        const TA am = x_amp[r][k];
+                        const int32_t *mp = a.dn_mv + (uint32_t)x_tab[r][k] * (uint32_t)ddn;
+                        int32_t m[4];
+                        if constexpr (FULL) {
+                            const int4 t4 = *reinterpret_cast<const int4 *>(mp + c);
+                            m[0] = t4.x; m[1] = t4.y; m[2] = t4.z; m[3] = t4.w;
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) m[j] = c + j < ddn ? mp[c + j] : -1;
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            if (m[j] < 0) continue;
+                            const TA v = (TA)src[(uint32_t)m[j] >> 1];
+                            acc[r][j] += (m[j] & 1) ? -am * v : am * v;
+                        }
+                    }
+                }
+            }
+        } else if (a.nx) {
+        // the rows' lists are ordered by down move, so each move table entry is
+        // loaded once for all rows of the tile
             int p[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) p[r] = 0;
@@ -733,7 +779,9 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
                     if constexpr (FULL) {
                         V v[4];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) v[i] = ld4(a.x + (int64_t)u_src[r][k + i] * ddn + c);
+                        for (int i = 0; i < 4; ++i)
+                            v[i] = GRP ? ld4(a.x + (uint32_t)((uint32_t)u_src[r][k + i] * (uint32_t)ddn + (uint32_t)c))
+                                       : ld4(a.x + (int64_t)u_src[r][k + i] * ddn + c);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const TA am = u_amp[r][k + i];
@@ -924,6 +972,78 @@ __global__ __launch_bounds__(BS) void k_upb(ApplyArgs<TX, TA> a, int64_t band, i
     }
 }
 
+// Band pass over a work list (grouped schedules): y[u, band] += (H_up (x) 1) x
+// for the rows [u0, u0 + rows) of one item and one band of BAND columns.
+// In the grouped order an up component's rows are contiguous and every up hop
+// stays inside the component, so the items of one (component, band) tile run
+// on one XCD one after another and the tile's slice of x (rows x BAND) stays
+// in that XCD's L2 while its rows read it.  BS threads: BAND/4 column lanes x
+// BS/(BAND/4) row lanes, four consecutive columns per thread (16-byte
+// accesses at element alignment); y is read and written non-temporally.
+template <typename TX, typename TA, int BS, int BAND>
+__global__ __launch_bounds__(BS) void k_upt(ApplyArgs<TX, TA> a) {
+    using V = typename V4<TX>::t;
+    constexpr int CL = BAND / 4, RL = BS / CL;
+    static_assert(BS % CL == 0, "band must divide the workgroup");
+    const int4 it = a.items[blockIdx.x];
+    const int64_t ddn = a.ddn;
+    const int cl = (int)threadIdx.x % CL, rl = (int)threadIdx.x / CL;
+    const int64_t c = (int64_t)it.z * BAND + 4 * cl;
+    if (it.y <= 0 || c >= ddn) return;  // no barriers in this kernel
+    const bool full = c + 4 <= ddn;
+    for (int r = rl; r < it.y; r += RL) {
+        const int64_t u = (int64_t)it.x + r;
+        TX *yr = a.y + u * ddn;
+        TA acc[4];
+        if (full) {
+            const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(yr + c));
+            acc[0] = (TA)v.x; acc[1] = (TA)v.y; acc[2] = (TA)v.z; acc[3] = (TA)v.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] = c + j < ddn ? (TA)yr[c + j] : (TA)0;
+        }
+        const int32_t hb = a.up_off[u], he = a.up_off[u + 1];
+        int32_t e = hb;
+        if (full) {
+            for (; e + 4 <= he; e += 4) {
+                V v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = ld4(a.x + (int64_t)a.up_tgt[e + i] * ddn + c);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const TA am = a.up_sa[e + i];
+                    acc[0] += am * (TA)v[i].x;
+                    acc[1] += am * (TA)v[i].y;
+                    acc[2] += am * (TA)v[i].z;
+                    acc[3] += am * (TA)v[i].w;
+                }
+            }
+            for (; e < he; ++e) {
+                const V v = ld4(a.x + (int64_t)a.up_tgt[e] * ddn + c);
+                const TA am = a.up_sa[e];
+                acc[0] += am * (TA)v.x;
+                acc[1] += am * (TA)v.y;
+                acc[2] += am * (TA)v.z;
+                acc[3] += am * (TA)v.w;
+            }
+            V o;
+            o.x = (TX)acc[0]; o.y = (TX)acc[1]; o.z = (TX)acc[2]; o.w = (TX)acc[3];
+            st4<TX, true>(yr + c, o);
+        } else {
+            for (; e < he; ++e) {
+                const TX *row = a.x + (int64_t)a.up_tgt[e] * ddn;
+                const TA am = a.up_sa[e];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (c + j < ddn) acc[j] += am * (TA)row[c + j];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (c + j < ddn) yr[c + j] = (TX)acc[j];
+        }
+    }
+}
+
 // ---------------------------------------------------------- variant table --
 // kind 0: single pass.  kind 1: two passes (row-local, then banded up spin).
 struct Variant {
@@ -950,6 +1070,14 @@ static const Variant kVariants[] = {
     {8, 4, 512, 256, "csx_rr4_rw32_band256", 0, 8},
     {8, 2, 1024, 512, "csx_rr2_b1024_rw32_band512", 0, 8},
     {8, 2, 1024, 256, "csx_rr2_b1024_rw64_band256", 0, 8},
+    // grouped basis order only: tile-major work lists over (up component,
+    // down window) tiles, windows = whole down components
+    {10, 2, 512, 0, "grp_rt_r2_b512"},      {10, 4, 512, 0, "grp_rt_r4_b512"},
+    {10, 1, 512, 0, "grp_rt_r1_b512"},
+    // grouped two passes: row pass (diagonal, 1 (x) H_dn, four-fermion terms)
+    // + band pass of H_up (x) 1 over (up component, band) tiles
+    {11, 2, 512, 128, "grp2_rt_r2_band128", 0, 32}, {11, 2, 512, 64, "grp2_rt_r2_band64", 0, 32},
+    {11, 1, 512, 128, "grp2_rt_r1_band128", 0, 32},
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static constexpr int64_t kDynBudget = 163840 - 8192;  // LDS left for the staged x block
@@ -993,6 +1121,33 @@ static std::vector<int2> plan_windows(const std::vector<uint32_t> &st, int ns, i
     return w;
 }
 
+// Windows of a grouped handle: consecutive down components merged greedily up
+// to `cap` states (every down hop stays inside its component); a component
+// larger than `cap` is cut into equal parts.
+static std::vector<int2> plan_windows_grouped(const std::vector<int32_t> &coff, int64_t cap) {
+    std::vector<int2> w;
+    int64_t cs = 0, cl = 0;
+    for (size_t k = 0; k + 1 < coff.size(); ++k) {
+        const int64_t a = coff[k], n = coff[k + 1] - coff[k];
+        if (n > cap) {
+            if (cl > 0) w.push_back(make_int2((int)cs, (int)cl));
+            const int64_t parts = (n + cap - 1) / cap, step = (n + parts - 1) / parts;
+            for (int64_t q = a; q < a + n; q += step) w.push_back(make_int2((int)q, (int)std::min(step, a + n - q)));
+            cs = a + n;
+            cl = 0;
+            continue;
+        }
+        if (cl + n > cap) {
+            w.push_back(make_int2((int)cs, (int)cl));
+            cs = a;
+            cl = 0;
+        }
+        cl += n;
+    }
+    if (cl > 0) w.push_back(make_int2((int)cs, (int)cl));
+    return w;
+}
+
 static const int2 *windows_for(ed_ham_s *h, int64_t cap, int *nwin, int *wmax) {
     for (size_t i = 0; i < h->windows.size(); ++i)
         if (h->windows[i].first == cap) {
@@ -1000,7 +1155,8 @@ static const int2 *windows_for(ed_ham_s *h, int64_t cap, int *nwin, int *wmax) {
             *wmax = h->window_counts[2 * i + 1];
             return h->windows[i].second->as<int2>();
         }
-    std::vector<int2> w = plan_windows(h->dn_states_host, h->ns, cap);
+    std::vector<int2> w = h->grouped ? plan_windows_grouped(h->comp_off[1], cap)
+                                     : plan_windows(h->dn_states_host, h->ns, cap);
     int mx = 0;
     for (auto &v : w) mx = std::max(mx, v.y);
     DevMem *m = new DevMem();
@@ -1012,6 +1168,59 @@ static const int2 *windows_for(ed_ham_s *h, int64_t cap, int *nwin, int *wmax) {
     *nwin = (int)w.size();
     *wmax = mx;
     return m->as<int2>();
+}
+
+// Work list of a grouped schedule over column ranges `cols` (windows or
+// bands): tiles (up component A, column range) in order, each cut into items
+// of at most `rows` consecutive rows of A.  The list is split into 8 runs of
+// about equal work (rows x columns) and run x is laid out at workgroup indices
+// x, x + 8, x + 16, ..., so that the round-robin dispatch of workgroups over
+// the 8 XCDs gives each XCD one run: the items of a tile then share one L2.
+// Shorter runs are padded with empty items.
+static const int4 *items_cached(const ed_ham_s *h, int64_t key, int64_t *count) {
+    for (size_t i = 0; i < h->items.size(); ++i)
+        if (h->items[i].first == key) {
+            *count = h->item_counts[i];
+            return h->items[i].second->as<int4>();
+        }
+    return nullptr;
+}
+
+static const int4 *items_for(ed_ham_s *h, int64_t key, const std::vector<int64_t> &cols, int rows,
+                             int64_t *count) {
+    if (const int4 *c = items_cached(h, key, count)) return c;
+    const std::vector<int32_t> &co = h->comp_off[0];
+    std::vector<int4> L;
+    std::vector<double> cost;
+    for (size_t A = 0; A + 1 < co.size(); ++A)
+        for (size_t w = 0; w < cols.size(); ++w)
+            for (int64_t u = co[A]; u < co[A + 1]; u += rows) {
+                const int nr = (int)std::min<int64_t>(rows, co[A + 1] - u);
+                L.push_back(make_int4((int)u, nr, (int)w, 0));
+                cost.push_back((double)nr * (double)cols[w]);
+            }
+    double total = 0.0;
+    for (double c : cost) total += c;
+    constexpr int kX = 8;
+    std::vector<std::vector<int4>> run(kX);
+    double acc = 0.0;
+    for (size_t i = 0; i < L.size(); ++i) {
+        const int x = std::min(kX - 1, (int)(acc / total * kX));
+        run[x].push_back(L[i]);
+        acc += cost[i];
+    }
+    size_t len = 1;
+    for (auto &r : run) len = std::max(len, r.size());
+    std::vector<int4> out(len * kX, make_int4(0, 0, 0, 0));
+    for (int x = 0; x < kX; ++x)
+        for (size_t i = 0; i < run[x].size(); ++i) out[x + kX * i] = run[x][i];
+    DevMem *m = new DevMem();
+    m->alloc(out.size() * sizeof(int4));
+    ED_HIP(hipMemcpy(m->p, out.data(), out.size() * sizeof(int4), hipMemcpyHostToDevice));
+    h->items.push_back({key, m});
+    h->item_counts.push_back((int64_t)out.size());
+    *count = (int64_t)out.size();
+    return m->as<int4>();
 }
 
 template <typename TX, typename TA>
@@ -1064,6 +1273,7 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.xl_amp = h->xl_amp64.as<double>();
     a.partials = partials;
     a.theta = theta;
+    a.items = nullptr;
     return a;
 }
 
@@ -1114,6 +1324,7 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.xl_amp = h->xl_amp32.as<float>();
     a.partials = partials;
     a.theta = theta;
+    a.items = nullptr;
     return a;
 }
 
@@ -1158,8 +1369,10 @@ static int64_t launch_rw(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_
     return G * nwin;
 }
 
-template <typename TX, typename TA, int R, int BS>
-static void launch_rt(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t wcap) {
+// tiled = true: tile-major work list (grouped handles); UPX = false: row pass
+// of a two-pass schedule (everything but H_up (x) 1)
+template <typename TX, typename TA, int R, int BS, bool UPX = true>
+static void launch_rt(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t wcap, bool tiled = false) {
     int nwin = 0, wmax = 0;
     const int64_t amp_bytes = (int64_t)h->sp[1].namp * (int64_t)sizeof(TA) + 16;
     int64_t cap = (kDynBudget - amp_bytes) / (int64_t)(R * sizeof(TX));
@@ -1167,11 +1380,46 @@ static void launch_rt(ed_ham_s *h, ApplyArgs<TX, TA> a, hipStream_t s, int64_t w
     a.win = windows_for(h, cap, &nwin, &wmax);
     a.nwin = nwin;
     a.wmax = wmax;
-    const int64_t G = (a.dup + R - 1) / R;
+    int64_t nblk = ((a.dup + R - 1) / R) * nwin;
+    if (tiled) {
+        const int64_t key = (int64_t)1 << 40 | (int64_t)R << 32 | cap;
+        a.items = items_cached(h, key, &nblk);
+        if (!a.items) {
+            std::vector<int2> w((size_t)nwin);
+            ED_HIP(hipMemcpy(w.data(), a.win, w.size() * sizeof(int2), hipMemcpyDeviceToHost));
+            std::vector<int64_t> cols;
+            for (auto &v : w) cols.push_back(v.y);
+            a.items = items_for(h, key, cols, R, &nblk);
+        }
+    }
     const size_t shm = (((size_t)R * (size_t)wmax * sizeof(TX) + 15) & ~(size_t)15) + (size_t)amp_bytes;
-    auto kern = k_rt<TX, TA, R, BS, true, true>;
-    allow_lds(kern);
-    kern<<<(unsigned)(G * nwin), BS, shm, s>>>(a);
+    if (tiled) {
+        auto kern = k_rt<TX, TA, R, BS, UPX, true, true>;
+        allow_lds(kern);
+        kern<<<(unsigned)nblk, BS, shm, s>>>(a);
+    } else {
+        auto kern = k_rt<TX, TA, R, BS, UPX, true>;
+        allow_lds(kern);
+        kern<<<(unsigned)nblk, BS, shm, s>>>(a);
+    }
+    ED_LAUNCH_CHECK();
+}
+
+// band pass of the grouped two-pass schedules (work list over (component, band) tiles)
+template <typename TX, typename TA>
+static void launch_upt(ed_ham_s *h, ApplyArgs<TX, TA> a, int64_t band, int rows, hipStream_t s) {
+    const int64_t key = (int64_t)2 << 40 | (int64_t)rows << 32 | band;
+    int64_t n = 0;
+    a.items = items_cached(h, key, &n);
+    if (!a.items) {
+        const int64_t nb = (a.ddn + band - 1) / band;
+        std::vector<int64_t> cols((size_t)nb);
+        for (int64_t b = 0; b < nb; ++b) cols[b] = std::min(band, a.ddn - b * band);
+        a.items = items_for(h, key, cols, rows, &n);
+    }
+    if (band == 128) k_upt<TX, TA, 256, 128><<<(unsigned)n, 256, 0, s>>>(a);
+    else if (band == 64) k_upt<TX, TA, 256, 64><<<(unsigned)n, 256, 0, s>>>(a);
+    else fail(ED_EINVAL, "band pass: unsupported band %lld", (long long)band);
     ED_LAUNCH_CHECK();
 }
 
@@ -1262,6 +1510,18 @@ static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipSt
             launch_cs<TX, TA, 2, 0, false, 1024>(h, a, 64, s);
             launch_upb<TX, TA, true>(a, V.band, V.rw, s);
             break;
+        case 17: launch_rt<TX, TA, 2, 512>(h, a, s, 0, true); break;
+        case 18: launch_rt<TX, TA, 4, 512>(h, a, s, 0, true); break;
+        case 19: launch_rt<TX, TA, 1, 512>(h, a, s, 0, true); break;
+        case 20:
+        case 21:
+            launch_rt<TX, TA, 2, 512, false>(h, a, s, 0, true);
+            launch_upt<TX, TA>(h, a, V.band, V.rw, s);
+            break;
+        case 22:
+            launch_rt<TX, TA, 1, 512, false>(h, a, s, 0, true);
+            launch_upt<TX, TA>(h, a, V.band, V.rw, s);
+            break;
         default: fail(ED_EINVAL, "bad apply variant %d", v);
     }
 }
@@ -1276,6 +1536,17 @@ static bool variant_fits(const ed_ham_s *h, int v, size_t elem) {
     if (V.kind == 8 && (h->sp[0].nnz == 0 || cs_kmax(h) == 0 || cs_nmv(h) < 0 || (h->nx > 0 && cs_xmax(h) == 0)))
         return false;
     if (V.kind == 8 && V.BS > 512 && cs_kmax(h) > 16) return false;
+    if (V.kind == 10 || V.kind == 11) {
+        if (!h->grouped || !h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->koff > 4 ||
+            h->D >= ((int64_t)1 << 32))
+            return false;
+        // the tile kernel needs every down component whole in its window
+        const int64_t amp_bytes = (int64_t)h->sp[1].namp * (int64_t)(h->prec == ED_FP64 ? 8 : 4) + 16;
+        const int64_t cap = (kDynBudget - amp_bytes) / (int64_t)(V.R * elem);
+        const std::vector<int32_t> &co = h->comp_off[1];
+        for (size_t k = 0; k + 1 < co.size(); ++k)
+            if (co[k + 1] - co[k] > cap) return false;
+    }
     return true;
 }
 

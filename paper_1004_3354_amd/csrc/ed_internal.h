@@ -197,8 +197,26 @@ struct ed_ham_s {
     std::vector<uint32_t> dn_states_host;           // for the LDS window plan
     std::vector<std::pair<int64_t, ed::DevMem *>> windows;  // (capacity, device int2 list)
     std::vector<int> window_counts;
+    // Grouped basis order.  On a handle built in that order (grouped = true)
+    // the states of each spin are ordered by connected component of the
+    // one-spin move graph (hops and same-spin two-body moves), components by
+    // their lowest rank, states within a component by rank; every index of its
+    // tables and vectors is a position in that order.  gperm[s][p] = rank of
+    // position p, gipos[s][r] = position of rank r, comp_off[s] = component
+    // boundaries.  A rank-order handle whose move graphs have several
+    // components owns such a twin (`twin`), which the solvers run on.
+    bool grouped = false;
+    ed::DevMem gperm[2], gipos[2];
+    std::vector<int32_t> comp_off[2];
+    ed_ham_s *twin = nullptr;
+    // tile-major, XCD-partitioned work lists of the grouped schedules:
+    // (key, device int4 list of (first row, rows, window or band, 0), count)
+    std::vector<std::pair<int64_t, ed::DevMem *>> items;
+    std::vector<int64_t> item_counts;
     ~ed_ham_s() {
         for (auto &w : windows) delete w.second;
+        for (auto &w : items) delete w.second;
+        delete twin;
     }
 };
 
@@ -250,6 +268,9 @@ struct ApplyArgs {
     const int2 *win;
     int nwin;
     int wmax;
+    // optional work list (grouped schedules): workgroup b takes items[b] =
+    // (first row, rows, window or band, 0); rows = 0 is an empty item
+    const int4 *items;
 };
 
 // Build all tables of a Hamiltonian handle (tables.hip).
@@ -261,6 +282,9 @@ void apply_launch_variant(ed_ham_s *h, int variant, const void *x, void *y, hipS
 int apply_variant_count(const ed_ham_s *h);
 const char *apply_variant_name(const ed_ham_s *h, int variant);
 void rayleigh_fp64(ed_ham_s *h, const void *x, double *rq, double *resid, hipStream_t s);
+
+// Rank order <-> grouped order of a vector (layout.hip): dir 0 = to grouped.
+void permute_vector(const ed_ham_s *g, const void *x, void *y, int dir, hipStream_t s);
 
 // Deterministic FP64 reductions (lanczos.hip)
 int reduce_blocks(int64_t n);

@@ -3,6 +3,7 @@
 #include "basis.hip"
 #include "tables.hip"
 #include "apply.hip"
+#include "layout.hip"
 #include "fill.hip"
 #include "lanczos.hip"
 #include "batched.hip"

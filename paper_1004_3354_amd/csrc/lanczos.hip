@@ -625,6 +625,7 @@ static void fill_defaults(ed_lanczos_opts &o) {
     o.check_every = 4;
     o.refine = 1;
     o.keep = 0;
+    o.layout = 0;
 }
 
 static ed_lanczos_opts effective(const ed_lanczos_opts *opts, int64_t D) {
@@ -632,6 +633,7 @@ static ed_lanczos_opts effective(const ed_lanczos_opts *opts, int64_t D) {
     fill_defaults(o);
     if (opts) o = *opts;
     if (o.max_iter <= 0) o.max_iter = 600;
+    if (o.layout != 1) o.layout = 0;
     if (o.max_basis < 0) o.max_basis = 0;      // 0: planned from the memory available
     if (o.max_basis == 1) o.max_basis = 2;
     if (o.max_basis > 1000) o.max_basis = 1000;
@@ -679,7 +681,8 @@ static size_t layout(Work &w, char *base, int64_t D, size_t elem, int m, int kma
 
 // ----------------------------------------------------------------- solver --
 struct Solver {
-    ed_ham_s *h;
+    ed_ham_s *h;               // the operator the iteration runs on
+    ed_ham_s *flat = nullptr;  // the rank-order handle when h is its grouped twin
     hipStream_t s;
     ed_lanczos_opts o;
     Work w;
@@ -733,6 +736,19 @@ struct Solver {
         if (nlock)
             ED_HIP(hipMemcpyAsync(w.sig2, lock_sig2.data(), (size_t)nlock * sizeof(double), hipMemcpyHostToDevice, s));
         ED_HIP(hipStreamSynchronize(s));
+    }
+    // caller vector (rank order) -> workspace slot (the operator's order)
+    void load_vector(const void *src, void *dst) {
+        if (flat) permute_vector(h, src, dst, 0, s);
+        else ED_HIP(hipMemcpyAsync(dst, src, (size_t)h->D * w.elem, hipMemcpyDeviceToDevice, s));
+    }
+    // a caller-owned vector converted in place between the two orders, through
+    // a free workspace slot (dir 0: to the grouped order, 1: back)
+    void convert_in_place(void *v, int dir) {
+        if (!flat) return;
+        void *tmp = w.slots[0];
+        ED_HIP(hipMemcpyAsync(tmp, v, (size_t)h->D * w.elem, hipMemcpyDeviceToDevice, s));
+        permute_vector(h, tmp, v, dir, s);
     }
     // vector norm^2 of y via a one-vector multidot with pointer slot `idx`
     double norm2_sync(int idx, const void *y) {
@@ -851,7 +867,7 @@ struct Solver {
     // k <= m steps (fewer when the Krylov space is exhausted, beta_h[k-1] = 0),
     // and ||v0||^2 in *v0n2.  Ground-state style storage: locked vectors none.
     int tridiag(const void *v0, int m, double *alpha_h, double *beta_h, double *v0n2) {
-        ED_HIP(hipMemcpyAsync(w.slots[0], v0, (size_t)h->D * w.elem, hipMemcpyDeviceToDevice, s));
+        load_vector(v0, w.slots[0]);
         // basis index i lives in slot i (full reorthogonalisation) or i mod 3
         // (three-term recurrence: only S_{j-1}, S_j and the new vector are read)
         std::vector<void *> kr((size_t)m + 1);
@@ -938,7 +954,7 @@ struct Solver {
                                                                h->prec == ED_FP32 ? 1 : 0);
             ED_LAUNCH_CHECK();
         } else {
-            ED_HIP(hipMemcpyAsync(w.slots[0], v0, (size_t)h->D * w.elem, hipMemcpyDeviceToDevice, s));
+            load_vector(v0, w.slots[0]);
         }
         std::vector<void *> kr(w.slots.begin(), w.slots.end());
         upload_pointers(kr);
@@ -1111,13 +1127,15 @@ static int plan_basis(const ed_ham_s *h, ed_lanczos_opts o, int k, bool locked_i
     return lo;
 }
 
-// Device memory a new workspace may take: what the runtime reports free, less
-// a reserve for the library's own tables and the caller's other buffers.
-static size_t device_budget() {
+// Device memory a new workspace may take: what the runtime reports free (or,
+// with total = true, the device's capacity), less a reserve for the library's
+// own tables and the caller's other buffers.
+static size_t device_budget(bool total = false) {
     size_t fr = 0, tot = 0;
     ED_HIP(hipMemGetInfo(&fr, &tot));
     const size_t reserve = std::max<size_t>((size_t)1 << 30, tot / 50);
-    return fr > reserve ? fr - reserve : 0;
+    const size_t avail = total ? tot : fr;
+    return avail > reserve ? avail - reserve : 0;
 }
 
 // Options with the basis size resolved: max_basis = 0 is planned against
@@ -1151,13 +1169,14 @@ extern "C" ed_status ed_workspace_bytes(ed_ham_t h, const ed_lanczos_opts *opts,
         if (k < 1 || (int64_t)k > h->D) fail(ED_EINVAL, "ed_workspace_bytes: k=%d outside [1, D=%lld]", k, (long long)h->D);
         if (k > 200) fail(ED_EINVAL, "ed_workspace_bytes: k=%d above 200", k);
         DeviceGuard g(h->device);
-        const size_t budget = device_budget();
-        const ed_lanczos_opts o = resolve(h, opts, k, true, budget);
+        // a planned basis must fit the memory free now; an explicit one the device
+        const ed_lanczos_opts o = resolve(h, opts, k, true, device_budget());
         *bytes = ws_needed(h, o, k, true);
-        if (*bytes > budget)
+        const size_t cap = device_budget(true);
+        if (*bytes > cap)
             fail(ED_ENOMEM, "workspace of %zu bytes (%d basis vectors of %lld elements) exceeds the %zu bytes "
-                 "available on the device; use a smaller max_basis or max_basis = 0 to plan it",
-                 *bytes, o.max_basis, (long long)h->D, budget);
+                 "the device can hold; use a smaller max_basis or max_basis = 0 to plan it",
+                 *bytes, o.max_basis, (long long)h->D, cap);
     });
 }
 
@@ -1185,17 +1204,22 @@ static ed_status solve(ed_ham_t h, int k, const ed_lanczos_opts *opts, const voi
             fail(ED_EINVAL, "k0=%d outside [0, k=%d) or no eigenvector array to continue from", k0, k);
         DeviceGuard g(h->device);
         Solver sv;
-        sv.h = h;
         sv.s = (hipStream_t)stream;
         // eigenpair e runs cycles of at most D - e steps (the deflated space)
         if (k > 200) fail(ED_EINVAL, "k=%d above 200", k);
         const bool locked_in_ws = (evecs == nullptr);
         sv.o = resolve(h, opts, k, locked_in_ws, ws_bytes);
+        // run on the grouped twin when there is one (same operator, basis
+        // order by components of the move graphs); vectors are converted at
+        // the boundary
+        sv.h = (sv.o.layout == 0 && h->twin) ? h->twin : h;
+        if (sv.h != h) sv.flat = h;
         const size_t need = ws_needed(h, sv.o, k, locked_in_ws);
         if (ws_bytes < need) fail(ED_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
         layout(sv.w, (char *)ws, h->D, h->prec == ED_FP64 ? 8 : 4, sv.o.max_basis, k, locked_in_ws);
         if (!locked_in_ws)
             for (int i = 0; i < k; ++i) sv.w.locked[i] = (char *)evecs + (size_t)i * h->D * sv.w.elem;
+        for (int e = 0; e < k0; ++e) sv.convert_in_place(sv.w.locked[e], 0);  // given vectors
         for (int e = 0; e < k; ++e) {
             if (e < k0) {  // given: lock it as it is
                 sv.nlock = e;
@@ -1232,7 +1256,9 @@ static ed_status solve(ed_ham_t h, int k, const ed_lanczos_opts *opts, const voi
         // already ascending up to rounding; report them sorted with vectors kept
         // in discovery order only if no vectors were requested
         if (!evecs) std::sort(evals, evals + k);
-        (void)k0;
+        else
+            for (int e = 0; e < k; ++e) sv.convert_in_place(sv.w.locked[e], 1);
+        ED_HIP(hipStreamSynchronize(sv.s));
     });
     if (st != ED_OK) return st;
     return result;
@@ -1253,11 +1279,12 @@ extern "C" ed_status ed_lanczos_tridiag(ed_ham_t h, const ed_lanczos_opts *opts,
             fail(ED_EINVAL, "m=%d outside [1, min(D=%lld, %d)]", m, (long long)h->D, kMaxVec - 2);
         DeviceGuard g(h->device);
         Solver sv;
-        sv.h = h;
         sv.s = (hipStream_t)stream;
         sv.o = effective(opts, h->D);
         sv.o.max_basis = m;
         sv.o.keep = 0;
+        sv.h = (sv.o.layout == 0 && h->twin) ? h->twin : h;
+        if (sv.h != h) sv.flat = h;
         const size_t need = tridiag_ws_needed(h, sv.o, m);
         if (ws_bytes < need) fail(ED_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
         layout(sv.w, (char *)ws, h->D, h->prec == ED_FP64 ? 8 : 4, m, 1, true,

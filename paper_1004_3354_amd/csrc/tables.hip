@@ -92,10 +92,12 @@ __global__ void k_hop_count(const uint32_t *st, int64_t dim, const int2 *pairs, 
     }
 }
 
+// ipos (nullptr = identity): position of each rank in the handle's basis order
 __global__ void k_hop_fill(const uint32_t *st, int64_t dim, int ns, int n, const int2 *pairs,
                            const double *pamp, int np, const int4 *quads, const double *qamp, int nq,
                            const int64_t *off64, int32_t *off,
-                           int32_t *tgt, int8_t *sgn, double *amp, double *sa64, float *sa32) {
+                           int32_t *tgt, int8_t *sgn, double *amp, double *sa64, float *sa32,
+                           const int32_t *ipos) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < dim;
          r += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t s = st[r];
@@ -107,7 +109,8 @@ __global__ void k_hop_fill(const uint32_t *st, int64_t dim, int ns, int n, const
             const int i = pairs[q].x, j = pairs[q].y;
             if (!(((s >> j) & 1u) && !((s >> i) & 1u))) continue;
             const uint32_t s2 = s ^ (1u << i) ^ (1u << j);
-            const int32_t t = (int32_t)rank_state(s2, ns, n);
+            int32_t t = (int32_t)rank_state(s2, ns, n);
+            if (ipos) t = ipos[t];
             const int8_t sg = (__popc(s & between_mask(i, j)) & 1) ? (int8_t)-1 : (int8_t)1;
             // insertion into the sorted run [a, k)
             int64_t p = k;
@@ -126,7 +129,8 @@ __global__ void k_hop_fill(const uint32_t *st, int64_t dim, int ns, int n, const
             uint32_t s2;
             int ng;
             if (!two_body_move(s, quads[q], &s2, &ng)) continue;
-            const int32_t t = (int32_t)rank_state(s2, ns, n);
+            int32_t t = (int32_t)rank_state(s2, ns, n);
+            if (ipos) t = ipos[t];
             int64_t p = k;
             while (p > a && tgt[p - 1] > t) {
                 tgt[p] = tgt[p - 1];
@@ -227,7 +231,9 @@ __global__ void k_cidx(const uint32_t *st, int64_t dim, const int *sites, int k,
 }
 
 // move table: electron src -> dst on every state: (rank << 1 | sign bit) or -1
-__global__ void k_move(const uint32_t *st, int64_t dim, int ns, int n, int src, int dst, int32_t *out) {
+// (position instead of rank when ipos is given)
+__global__ void k_move(const uint32_t *st, int64_t dim, int ns, int n, int src, int dst, int32_t *out,
+                       const int32_t *ipos) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < dim;
          r += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t s = st[r];
@@ -236,7 +242,8 @@ __global__ void k_move(const uint32_t *st, int64_t dim, int ns, int n, int src, 
             if ((s >> src) & 1u) v = (int32_t)(r << 1);  // c+_i c_i = n_i: same state, no sign
         } else if (((s >> src) & 1u) && !((s >> dst) & 1u)) {
             const uint32_t s2 = s ^ (1u << src) ^ (1u << dst);
-            const int64_t t = rank_state(s2, ns, n);
+            int64_t t = rank_state(s2, ns, n);
+            if (ipos) t = ipos[t];
             const int neg = __popc(s & between_mask(src, dst)) & 1;
             v = (int32_t)((t << 1) | neg);
         }
@@ -352,7 +359,8 @@ static void build_spin(ed_ham_s *h, int s, const BasisData &b, const ed_params *
     k_hop_fill<<<g, 256>>>(t.states.as<uint32_t>(), dim, ns, t.n, dpairs.as<int2>(), dpamp.as<double>(),
                            (int)pairs.size(), dquads.as<int4>(), dqamp.as<double>(), (int)quads.size(),
                            off64.as<int64_t>(), t.off.as<int32_t>(), t.tgt.as<int32_t>(),
-                           t.sgn.as<int8_t>(), t.amp.as<double>(), t.sa64.as<double>(), t.sa32.as<float>());
+                           t.sgn.as<int8_t>(), t.amp.as<double>(), t.sa64.as<double>(), t.sa32.as<float>(),
+                           h->grouped ? h->gipos[s].as<int32_t>() : nullptr);
     ED_LAUNCH_CHECK();
 
     // sliced ELL
@@ -573,7 +581,8 @@ static void build_xterms(ed_ham_s *h, const ed_params *p) {
         t.mv.alloc((size_t)std::max(t.nmv, 1) * (size_t)t.dim * sizeof(int32_t));
         for (int q = 0; q < t.nmv; ++q) {
             k_move<<<grid_for(t.dim, 256, 1 << 16), 256>>>(t.states.as<uint32_t>(), t.dim, t.ns, t.n, t.mv_src[q],
-                                                          t.mv_dst[q], t.mv.as<int32_t>() + (size_t)q * t.dim);
+                                                          t.mv_dst[q], t.mv.as<int32_t>() + (size_t)q * t.dim,
+                                                          h->grouped ? h->gipos[s].as<int32_t>() : nullptr);
             ED_LAUNCH_CHECK();
         }
     }
@@ -716,6 +725,86 @@ static void validate(const ed_params *p, int ns) {
     }
 }
 
+// Connected components of one spin's move graph (the hop table, which also
+// holds the same-spin two-body moves) by union-find; the grouped order lists
+// the components by their lowest rank and each component's states by rank.
+// Returns the number of components; perm[p] = rank at position p.
+static int component_order(const SpinTab &t, std::vector<int32_t> &perm, std::vector<int32_t> &comp_off) {
+    const int64_t dim = t.dim;
+    std::vector<int32_t> off((size_t)dim + 1), tgt((size_t)std::max<int64_t>(t.nnz, 1));
+    ED_HIP(hipMemcpy(off.data(), t.off.p, off.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (t.nnz > 0) ED_HIP(hipMemcpy(tgt.data(), t.tgt.p, (size_t)t.nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> par((size_t)dim);
+    for (int64_t r = 0; r < dim; ++r) par[r] = (int32_t)r;
+    auto find = [&](int32_t x) {
+        while (par[x] != x) {
+            par[x] = par[par[x]];
+            x = par[x];
+        }
+        return x;
+    };
+    for (int64_t r = 0; r < dim; ++r)
+        for (int32_t e = off[r]; e < off[r + 1]; ++e) {
+            int32_t a = find((int32_t)r), c = find(tgt[e]);
+            if (a == c) continue;
+            if (a < c) par[c] = a;  // the root is the lowest rank of the component
+            else par[a] = c;
+        }
+    // components in order of their root (lowest rank), states by rank
+    std::vector<int32_t> root((size_t)dim), cnt((size_t)dim, 0);
+    for (int64_t r = 0; r < dim; ++r) {
+        root[r] = find((int32_t)r);
+        ++cnt[root[r]];
+    }
+    std::vector<int32_t> start((size_t)dim, -1);
+    comp_off.assign(1, 0);
+    for (int64_t r = 0; r < dim; ++r)
+        if (root[r] == r) {
+            start[r] = comp_off.back();
+            comp_off.push_back(comp_off.back() + cnt[r]);
+        }
+    perm.assign((size_t)dim, 0);
+    for (int64_t r = 0; r < dim; ++r) perm[start[root[r]]++] = (int32_t)r;
+    return (int)comp_off.size() - 1;
+}
+
+// The same operator in the grouped basis order (see ed_ham_s), built when a
+// one-spin move graph has more than one component.
+static void build_twin(ed_ham_s *h, const ed_params *p, const BasisData &b) {
+    std::vector<int32_t> perm[2], coff[2];
+    int nc[2];
+    for (int s = 0; s < 2; ++s) nc[s] = component_order(h->sp[s], perm[s], coff[s]);
+    if (nc[0] < 2 && nc[1] < 2) return;
+    ed_ham_s *g = new ed_ham_s();
+    try {
+        g->device = h->device;
+        g->prec = h->prec;
+        g->grouped = true;
+        BasisData bg;
+        bg.ns = b.ns;
+        for (int s = 0; s < 2; ++s) {
+            bg.n[s] = b.n[s];
+            bg.dim[s] = b.dim[s];
+            std::vector<uint32_t> st((size_t)b.dim[s]), sg((size_t)b.dim[s]);
+            ED_HIP(hipMemcpy(st.data(), b.states[s].p, st.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+            std::vector<int32_t> ip((size_t)b.dim[s]);
+            for (int64_t q = 0; q < b.dim[s]; ++q) {
+                sg[q] = st[perm[s][q]];
+                ip[perm[s][q]] = (int32_t)q;
+            }
+            upload(bg.states[s], sg);
+            upload(g->gperm[s], perm[s]);
+            upload(g->gipos[s], ip);
+            g->comp_off[s] = coff[s];
+        }
+        build_tables(g, p, bg);
+    } catch (...) {
+        delete g;
+        throw;
+    }
+    h->twin = g;
+}
+
 void build_tables(ed_ham_s *h, const ed_params *p, const BasisData &b) {
     validate(p, b.ns);
     ensure_device_binomials();
@@ -733,6 +822,7 @@ void build_tables(ed_ham_s *h, const ed_params *p, const BasisData &b) {
     h->dn_states_host.resize((size_t)h->ddn);
     ED_HIP(hipMemcpy(h->dn_states_host.data(), h->sp[1].states.p, (size_t)h->ddn * sizeof(uint32_t),
                      hipMemcpyDeviceToHost));
+    if (!h->grouped) build_twin(h, p, b);
 }
 
 }  // namespace ed
@@ -794,7 +884,7 @@ extern "C" ed_status ed_hop_table(ed_ham_t h, int spin, int64_t *off, int32_t *t
 }
 
 extern "C" void ed_ham_free(ed_ham_t h) {
-    if (!h) return;
+    if (!h || h->grouped) return;  // a grouped twin belongs to its rank-order handle
     try {
         DeviceGuard g(h->device);
         (void)hipDeviceSynchronize();

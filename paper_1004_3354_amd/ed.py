@@ -50,7 +50,7 @@ class ed_params(ctypes.Structure):
 class ed_lanczos_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("max_basis", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("reorth", ctypes.c_int32), ("check_every", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("keep", ctypes.c_int32)]
+                ("keep", ctypes.c_int32), ("layout", ctypes.c_int32)]
 
 
 class ed_info(ctypes.Structure):
@@ -89,6 +89,10 @@ _sig("ed_apply_H_variant", ctypes.c_int, [_p, ctypes.c_int, _p, _p, _p])
 _sig("ed_rayleigh", ctypes.c_int, [_p, _p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _p])
 _sig("ed_fill_random", ctypes.c_int, [_p, _i64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _p])
 _sig("ed_ham_free", None, [_p])
+_sig("ed_ham_grouped", ctypes.c_int, [_p, ctypes.POINTER(_p)])
+_sig("ed_grouped_order", ctypes.c_int, [_p, ctypes.c_int, _p])
+_sig("ed_to_grouped", ctypes.c_int, [_p, _p, _p, _p])
+_sig("ed_from_grouped", ctypes.c_int, [_p, _p, _p, _p])
 _sig("ed_lanczos_defaults", None, [ctypes.POINTER(ed_lanczos_opts)])
 _sig("ed_workspace_bytes", ctypes.c_int, [_p, ctypes.POINTER(ed_lanczos_opts), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_size_t)])
@@ -138,11 +142,12 @@ def _dev_ptr(t) -> int:
     return t.data_ptr()
 
 
-def options(max_iter=None, max_basis=None, tol=None, reorth=None, check_every=None, refine=None, keep=None):
+def options(max_iter=None, max_basis=None, tol=None, reorth=None, check_every=None, refine=None, keep=None,
+            layout=None):
     o = ed_lanczos_opts()
     _lib.ed_lanczos_defaults(ctypes.byref(o))
     for k, v in (("max_iter", max_iter), ("max_basis", max_basis), ("tol", tol), ("reorth", reorth),
-                 ("check_every", check_every), ("refine", refine), ("keep", keep)):
+                 ("check_every", check_every), ("refine", refine), ("keep", keep), ("layout", layout)):
         if v is not None:
             setattr(o, k, v)
     return o
@@ -247,6 +252,9 @@ class Hamiltonian:
 
     def workspace_bytes(self, opts=None, k: int = 1) -> int:
         o = opts if opts is not None else options()
+        if o.max_basis == 0:   # planned from free device memory: hand torch's cached blocks back first
+            import torch
+            torch.cuda.empty_cache()
         n = ctypes.c_size_t()
         _check(_lib.ed_workspace_bytes(self._h, ctypes.byref(o), k, ctypes.byref(n)))
         return n.value
@@ -318,10 +326,36 @@ class Hamiltonian:
                                        _stream(stream)))
         return a[:k.value].copy(), b[:k.value].copy(), n2.value
 
+    def grouped(self) -> Optional["Hamiltonian"]:
+        """The same operator in the grouped basis order (a borrowed twin handle
+        that lives as long as this one), or None when there is none."""
+        g = _p()
+        _check(_lib.ed_ham_grouped(self._h, ctypes.byref(g)))
+        if not g.value:
+            return None
+        if g.value == self._h.value:
+            return self
+        t = Hamiltonian.__new__(Hamiltonian)
+        t._h, t._owner, t._borrowed = g, self, True
+        t.precision, t.dup, t.ddn, t.D = self.precision, self.dup, self.ddn, self.D
+        return t
+
+    def grouped_order(self, spin: int) -> np.ndarray:
+        """rank_of_position[p] of this (twin) handle's grouped order."""
+        out = np.empty(self.dup if spin == 0 else self.ddn, dtype=np.int32)
+        _check(_lib.ed_grouped_order(self._h, spin, out.ctypes.data_as(_p)))
+        return out
+
+    def to_grouped(self, x, y, stream=None):
+        _check(_lib.ed_to_grouped(self._h, _dev_ptr(x), _dev_ptr(y), _stream(stream)))
+
+    def from_grouped(self, x, y, stream=None):
+        _check(_lib.ed_from_grouped(self._h, _dev_ptr(x), _dev_ptr(y), _stream(stream)))
+
     def close(self):
-        if self._h:
+        if self._h and not getattr(self, "_borrowed", False):
             _lib.ed_ham_free(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:

@@ -227,3 +227,116 @@ def test_errors_reported():
         ed.Hamiltonian(bad, b6, ed.ED_FP64)
     with pytest.raises(ed.EDError):
         H.workspace_bytes(None, k=b.D + 1)
+
+
+# ------------------------------------------------------------ grouped order --
+# Models whose one-spin move graphs split into components (each orbital of the
+# three-orbital impurity hops only to its own bath levels): the library keeps a
+# twin handle with the basis ordered by component.  Its H.v, in that order,
+# must be the same operator: x is converted to the grouped order, multiplied
+# with every schedule that fits the twin, converted back and compared with the
+# oracle's product in rank order.
+GROUPED = [c for c in SMALL + EDGE if c[0].startswith("kan")]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("name,phys,sec_nn", GROUPED, ids=[c[0] for c in GROUPED])
+def test_grouped_apply_parity_all_schedules(name, phys, sec_nn, prec):
+    ed = gpu_ed()
+    nup, ndn = sec_nn
+    b, H = build(phys, nup, ndn, prec)
+    G = H.grouped()
+    assert G is not None and G.D == H.D
+    sec = sector(phys, nup, ndn)
+    sec_abs = sector(phys, nup, ndn, absval=True)
+    dt = torch.float64 if prec == ed.ED_FP64 else torch.float32
+    xd = torch.from_numpy(_x(sec.D, 91 + nup * 13 + ndn)).to(DEV, dt)
+    xin = xd.double().cpu().numpy()
+    y_ref = sec.spmv(xin)
+    ahx = abs_apply(sec_abs, np.abs(xin))
+    nterm = int(np.max(np.diff(sec_abs.csr()[0]))) if sec.D > 0 else 1
+    tol = bound(ahx, nterm, U64 if prec == ed.ED_FP64 else U32)
+    xg = torch.empty_like(xd)
+    H.to_grouped(xd, xg)
+    checked = 0
+    for v in range(ed.variant_count()):
+        if not G.variant_fits(v):
+            continue
+        yg = torch.full_like(xd, float("nan"))
+        G.apply_variant(v, xg, yg)
+        y = torch.empty_like(xd)
+        H.from_grouped(yg, y)
+        torch.cuda.synchronize()
+        err = np.abs(y.double().cpu().numpy() - y_ref)
+        bad = np.nonzero(~(err <= tol))[0]
+        assert bad.size == 0, "variant %s: %d elements out of bound" % (ed.variant_name(v), bad.size)
+        checked += 1
+    assert checked >= 3
+    # the grouped-only schedules fit every such twin
+    assert any(ed.variant_name(v).startswith("grp") and G.variant_fits(v) for v in range(ed.variant_count()))
+
+
+@pytest.mark.parametrize("name,phys,sec_nn", GROUPED[:4], ids=[c[0] for c in GROUPED[:4]])
+def test_grouped_order_and_tables(name, phys, sec_nn):
+    """The grouped order is a permutation that keeps ranks ascending inside
+    each component, every hop of the twin stays inside its component, and the
+    twin's hop table translated back to ranks is the oracle's (bit for bit,
+    per row as a set of (target, sign, amplitude))."""
+    ed = gpu_ed()
+    nup, ndn = sec_nn
+    ns = int(phys["Ns"])
+    b, H = build(phys, nup, ndn, ed.ED_FP64)
+    G = H.grouped()
+    p = models.params_from_model(phys)
+    for s, n in ((0, nup), (1, ndn)):
+        perm = G.grouped_order(s).astype(np.int64)
+        D = len(perm)
+        assert np.array_equal(np.sort(perm), np.arange(D))
+        off, tgt, sgn, amp = G.hop_table(s)
+        o_off, o_tgt, o_sgn, o_amp = orc.onebody_table(ns, n, p["hop"][s])
+        # components = connected sets of positions under the twin's hops
+        comp = np.arange(D)
+        for _ in range(D):
+            changed = False
+            for i in range(D):
+                for e in range(off[i], off[i + 1]):
+                    m = min(comp[i], comp[tgt[e]])
+                    if comp[i] != m or comp[tgt[e]] != m:
+                        comp[i] = comp[tgt[e]] = m
+                        changed = True
+            if not changed:
+                break
+        # contiguous components, ranks ascending inside each
+        starts = np.nonzero(np.r_[True, comp[1:] != comp[:-1]])[0]
+        assert len(np.unique(comp)) == len(starts)
+        for a, z in zip(starts, np.r_[starts[1:], D]):
+            assert np.all(np.diff(perm[a:z]) > 0)
+        for i in range(D):
+            r = perm[i]
+            mine = sorted(zip(perm[tgt[off[i]:off[i + 1]]].tolist(), sgn[off[i]:off[i + 1]].tolist(),
+                              amp[off[i]:off[i + 1]].tolist()))
+            want = sorted(zip(o_tgt[o_off[r]:o_off[r + 1]].tolist(), o_sgn[o_off[r]:o_off[r + 1]].tolist(),
+                              o_amp[o_off[r]:o_off[r + 1]].tolist()))
+            assert mine == want, (s, i, r)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_solver_layouts_agree(prec):
+    """The default solver path iterates on the grouped twin; the rank-order
+    path gives the same ground state (energy and vector up to sign)."""
+    ed = gpu_ed()
+    phys, _ = wl.config(3)
+    b, H = build(phys, 6, 6, prec)
+    dt = torch.float64 if prec == 0 else torch.float32
+    v0 = torch.empty(H.D, dtype=dt, device=DEV)
+    ed.fill_random(v0, 5, 1)
+    out = []
+    for layout in (0, 1):
+        psi = torch.empty_like(v0)
+        e, info = H.lanczos_ground(v0, ed.options(tol=1e-12 if prec == 0 else 1e-7, layout=layout), psi=psi)
+        out.append((e, psi.double()))
+    (e0, p0), (e1, p1) = out
+    tol = 1e-10 if prec == 0 else 1e-6
+    assert abs(e0 - e1) <= tol * max(1.0, abs(e1))
+    ov = abs(float(torch.dot(p0, p1))) / float(p0.norm() * p1.norm())
+    assert ov >= 1.0 - (1e-10 if prec == 0 else 1e-5), ov
