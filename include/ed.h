@@ -176,6 +176,18 @@ ed_status ed_apply_H_variant(ed_ham_t h, int variant, const void *x, void *y, vo
  * H x evaluated in FP64 arithmetic and never stored.  Synchronous. */
 ed_status ed_rayleigh(ed_ham_t h, const void *x, double *rq, double *resid, void *stream);
 
+/* ed_rayleigh for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * result, with the per-workgroup partial sums in a static device array of
+ * 2^18 (a, b) pairs (4 MiB per GPU, held until the process ends) instead of a
+ * buffer the handle allocates.  The array holds D_up x (number of LDS windows
+ * of the down basis) pairs at most: EINVAL beyond that (use ed_rayleigh).  No
+ * device memory is allocated or freed.  Every call on one GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other threads, other streams)
+ * race; the partials are overwritten in full by each call, nothing needs to
+ * start at zero.  Synchronous. */
+ed_status ed_rayleigh_noalloc(ed_ham_t h, const void *x, double *rq, double *resid, void *stream);
+
 /* Fill a DEVICE vector with n numbers of the counter-based SplitMix64 stream
  * `seed` (element i uses output i, or outputs 2i and 2i+1): dist 0 = uniform on
  * [-1, 1), dist 1 = standard normal (Box-Muller).  precision ED_FP64 or ED_FP32

@@ -1641,13 +1641,39 @@ void ensure_redbuf(ed_ham_s *h, size_t doubles) {
     h->redbuf_doubles = doubles;
 }
 
-template <typename TX>
-static void rayleigh_impl(ed_ham_s *h, const void *x, double *rq, double *resid, hipStream_t s) {
+// Windows of the FP64-arithmetic apply of the Rayleigh quotient (the row
+// tiles of k_apply with one row and no packed table).
+static int64_t rayleigh_cap(const ed_ham_s *h) { return kDynBudget / (int64_t)(h->prec == ED_FP64 ? 8 : 4); }
+
+// Number of (a, b) partial pairs the Rayleigh quotient writes, from the cached
+// window plan only (-1 when it is not there yet).
+int64_t rayleigh_pairs_cached(const ed_ham_s *h) {
+    const int64_t cap = rayleigh_cap(h);
+    for (size_t i = 0; i < h->windows.size(); ++i)
+        if (h->windows[i].first == cap) return h->dup * (int64_t)h->window_counts[2 * i];
+    return -1;
+}
+
+// At handle creation: the window plan of the Rayleigh quotient and the LDS
+// attribute of its kernels, so that later calls allocate nothing for them.
+void prepare_rayleigh(ed_ham_s *h) {
     int nwin = 0, wmax = 0;
-    (void)windows_for(h, kDynBudget / (int64_t)sizeof(TX), &nwin, &wmax);
-    const int64_t nb = h->dup * (int64_t)nwin;
-    ensure_redbuf(h, (size_t)2 * nb + 8);
-    double *part = h->redbuf.as<double>();
+    (void)windows_for(h, rayleigh_cap(h), &nwin, &wmax);
+    if (h->prec == ED_FP64) {
+        allow_lds(k_apply<double, double, 1, 512, 1, true, false>);
+        allow_lds(k_apply<double, double, 1, 512, 2, true, false>);
+    } else {
+        allow_lds(k_apply<float, double, 1, 512, 1, true, false>);
+        allow_lds(k_apply<float, double, 1, 512, 2, true, false>);
+    }
+}
+
+// rq = <x,Hx>/<x,x>, resid = ||Hx - rq x|| / ||x|| with H x in FP64 arithmetic;
+// part: 2 nb + 2 doubles of device memory for the per-workgroup partials and
+// the two sums (nb = rayleigh_pairs_cached).
+template <typename TX>
+static void rayleigh_with(ed_ham_s *h, const void *x, double *part, int64_t nb, double *rq, double *resid,
+                          hipStream_t s) {
     double *out = part + 2 * nb;
     double hv[2];
     ApplyArgs<TX, double> a = make_args<TX, double>(h, x, nullptr, part, 0.0);
@@ -1669,11 +1695,22 @@ static void rayleigh_impl(ed_ham_s *h, const void *x, double *rq, double *resid,
     *resid = std::sqrt(r2[0] / hv[1]);
 }
 
-void rayleigh_fp64(ed_ham_s *h, const void *x, double *rq, double *resid, hipStream_t s) {
+void rayleigh_on(ed_ham_s *h, const void *x, double *part, int64_t nb, double *rq, double *resid, hipStream_t s) {
     if (h->prec == ED_FP64)
-        rayleigh_impl<double>(h, x, rq, resid, s);
+        rayleigh_with<double>(h, x, part, nb, rq, resid, s);
     else
-        rayleigh_impl<float>(h, x, rq, resid, s);
+        rayleigh_with<float>(h, x, part, nb, rq, resid, s);
+}
+
+// The handle's own reduction buffer (grown on demand).
+void rayleigh_fp64(ed_ham_s *h, const void *x, double *rq, double *resid, hipStream_t s) {
+    int64_t nb = rayleigh_pairs_cached(h);
+    if (nb < 0) {
+        prepare_rayleigh(h);
+        nb = rayleigh_pairs_cached(h);
+    }
+    ensure_redbuf(h, (size_t)2 * nb + 8);
+    rayleigh_on(h, x, h->redbuf.as<double>(), nb, rq, resid, s);
 }
 
 }  // namespace ed

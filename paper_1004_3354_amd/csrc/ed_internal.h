@@ -282,6 +282,9 @@ void apply_launch_variant(ed_ham_s *h, int variant, const void *x, void *y, hipS
 int apply_variant_count(const ed_ham_s *h);
 const char *apply_variant_name(const ed_ham_s *h, int variant);
 void rayleigh_fp64(ed_ham_s *h, const void *x, double *rq, double *resid, hipStream_t s);
+void prepare_rayleigh(ed_ham_s *h);
+int64_t rayleigh_pairs_cached(const ed_ham_s *h);
+void rayleigh_on(ed_ham_s *h, const void *x, double *part, int64_t nb, double *rq, double *resid, hipStream_t s);
 
 // Rank order <-> grouped order of a vector (layout.hip): dir 0 = to grouped.
 void permute_vector(const ed_ham_s *g, const void *x, void *y, int dir, hipStream_t s);

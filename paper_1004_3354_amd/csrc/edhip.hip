@@ -8,3 +8,4 @@
 #include "lanczos.hip"
 #include "batched.hip"
 #include "green.hip"
+#include "noalloc.hip"

@@ -841,6 +841,8 @@ extern "C" ed_status ed_ham_create(const ed_params *p, ed_basis_t b, int precisi
             h->device = b->device;
             h->prec = precision;
             build_tables(h, p, b->b);
+            prepare_rayleigh(h);
+            if (h->twin) prepare_rayleigh(h->twin);
         } catch (...) {
             delete h;
             throw;

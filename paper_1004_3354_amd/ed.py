@@ -88,6 +88,8 @@ _sig("ed_apply_current_variant", ctypes.c_int, [_p])
 _sig("ed_apply_H_variant", ctypes.c_int, [_p, ctypes.c_int, _p, _p, _p])
 _sig("ed_rayleigh", ctypes.c_int, [_p, _p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _p])
 _sig("ed_fill_random", ctypes.c_int, [_p, _i64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _p])
+_sig("ed_rayleigh_noalloc", ctypes.c_int, [_p, _p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                           _p])
 _sig("ed_ham_free", None, [_p])
 _sig("ed_ham_grouped", ctypes.c_int, [_p, ctypes.POINTER(_p)])
 _sig("ed_grouped_order", ctypes.c_int, [_p, ctypes.c_int, _p])
@@ -248,6 +250,11 @@ class Hamiltonian:
     def rayleigh(self, x, stream=None) -> Tuple[float, float]:
         rq, rs = ctypes.c_double(), ctypes.c_double()
         _check(_lib.ed_rayleigh(self._h, _dev_ptr(x), ctypes.byref(rq), ctypes.byref(rs), _stream(stream)))
+        return rq.value, rs.value
+
+    def rayleigh_noalloc(self, x, stream=None) -> Tuple[float, float]:
+        rq, rs = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.ed_rayleigh_noalloc(self._h, _dev_ptr(x), ctypes.byref(rq), ctypes.byref(rs), _stream(stream)))
         return rq.value, rs.value
 
     def workspace_bytes(self, opts=None, k: int = 1) -> int:
