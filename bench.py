@@ -95,39 +95,65 @@ def setup(cfg, prec, jprime=True):
     return phys, (nup, ndn), b, H, time.perf_counter() - t0
 
 
-def cpu_baseline(cfg, target_s=12.0):
-    """FP64 oracle on the host: literal operator-string rows of the same sector
-    evaluated without storing H, on a random sample of rows."""
+def _omp(n=None):
+    """Thread count of the OpenMP runtime the oracle's C core runs on (set when
+    n is given); the oracle and this process share one libgomp."""
+    import ctypes
+    try:
+        g = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+    if n is not None:
+        g.omp_set_num_threads(int(n))
+    return int(g.omp_get_max_threads())
+
+
+def cpu_baseline(cfg=2, max_steps=400, tol=1e-7):
+    """FP64 oracle on the host cores, in the paper's own format: the sector
+    matrix built from the literal operator strings into the CSR arrays of
+    Fig. 1 (the "setup" of Table 1, timed), the CSR product of Listing 1 (rows
+    over OpenMP threads; all cores, then one), and the oracle's three-term
+    Lanczos on that product to the ground energy with the stopping rule of the
+    GPU runs.  value = algorithmic GB/s of the all-core product (16 B per
+    output element, FP64), the unit of the headline."""
     import numpy as np
     import oracle as orc
     from paper_1004_3354_amd import workloads as wl
+    cores = len(os.sched_getaffinity(0))
+    _omp(cores)
     phys, sectors = wl.config(cfg)
     sec = orc.sector_for(phys, *sectors[0])
+    t0 = time.perf_counter()
+    row_ind, col_ind, H = sec.csr()
+    setup_s = time.perf_counter() - t0
+    nnz = int(row_ind[-1])
     x = wl.uniform_vector(wl.start_vector_seed(cfg), sec.D)
-    rng = np.random.default_rng(1)
-    n = 20000
-    rows = np.sort(rng.choice(sec.D, n, replace=False))
+    orc.spmv(row_ind, col_ind, H, x)                      # first touch
+    reps = 3
     t0 = time.perf_counter()
-    sec.rows_apply(rows, x)
-    dt = time.perf_counter() - t0
-    n = int(min(sec.D, max(n, n * target_s / max(dt, 1e-6))))
-    rows = np.arange(sec.D) if n == sec.D else np.sort(rng.choice(sec.D, n, replace=False))
+    for _ in range(reps):
+        orc.spmv(row_ind, col_ind, H, x)
+    spmv_s = (time.perf_counter() - t0) / reps
+    _omp(1)
     t0 = time.perf_counter()
-    sec.rows_apply(rows, x)
-    dt = time.perf_counter() - t0
-    threads = None
-    try:
-        import ctypes
-        threads = ctypes.CDLL("libgomp.so.1").omp_get_max_threads()
-    except OSError:
-        threads = len(os.sched_getaffinity(0))
-    rate = n / dt                       # rows (output elements) per second
-    return {"value": round(16.0 * rate / 1e9, 4), "unit": "GB/s (FP64 algorithmic: 16 B per output element)",
-            "cores": int(threads), "kind": "oracle",
-            "sample": ("%s of the N_s=15 sector, literal Jordan-Wigner operator strings per row "
-                       "(matrix-free oracle path), %.1f s"
-                       % ("all %d rows (one full H.v)" % n if n == sec.D else "%d random rows" % n, dt)),
-            "rows_per_s": round(rate, 1)}
+    orc.spmv(row_ind, col_ind, H, x)
+    spmv_1_s = time.perf_counter() - t0
+    _omp(cores)
+    v0 = wl.gaussian_vector(wl.start_vector_seed(cfg), sec.D)
+    t0 = time.perf_counter()
+    e0, _, info = orc.lanczos_ground(lambda v: orc.spmv(row_ind, col_ind, H, v), v0, max_iter=max_steps, tol=tol,
+                                     reorth=False, want_vector=False)
+    e0_s = time.perf_counter() - t0
+    rate = 16.0 * sec.D / spmv_s / 1e9
+    return {"value": round(rate, 3), "unit": "GB/s (FP64 algorithmic: 16 B per output element)",
+            "cores": cores, "kind": "oracle",
+            "sample": ("the whole N_s=15 sector (7,7), D=%d: CSR of Fig. 1 built from the literal operator strings "
+                       "(%d nonzeros, %.1f GB), Listing-1 product over %d threads" %
+                       (sec.D, nnz, (nnz * 16 + 8 * sec.D) / 1e9, cores)),
+            "setup_s": round(setup_s, 2), "spmv_csr_s": round(spmv_s, 4),
+            "single_thread": {"spmv_csr_s": round(spmv_1_s, 3), "value": round(16.0 * sec.D / spmv_1_s / 1e9, 3)},
+            "time_to_e0": {"seconds": round(e0_s, 2), "E0": e0, "iters": info["iters"], "tol": tol,
+                           "method": "three-term Lanczos on the CSR product (no reorthogonalisation)"}}
 
 
 def time_to_e0(cfg, precs, max_basis, tol, seed_idx, reorth=3, keep=0):
@@ -147,7 +173,7 @@ def time_to_e0(cfg, precs, max_basis, tol, seed_idx, reorth=3, keep=0):
         opts = ed.options(tol=tol, max_basis=m, reorth=reorth, keep=kp)
         ws = torch.empty(H.workspace_bytes(opts, 1), dtype=torch.uint8, device="cuda")
         y = ws[: b.D * v0.element_size()].view(dt)   # scratch: tune the schedule outside the timed region
-        H.apply(v0, y)
+        (H.grouped() or H).apply(v0, y)              # the solver iterates on the grouped twin when there is one
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         E, info = H.lanczos_ground(v0, opts, ws=ws, allow_noconv=True)
@@ -365,6 +391,77 @@ def pmc_pass(args):
                       "steps": args.steps, "copy_bytes_each_way": 4 * b.D}), flush=True)
 
 
+def apply_leg(cfg, prec, steps, warmup=2):
+    """Tuned H.v of one sector in the rank order (ed_apply_H on the handle) and
+    in the grouped order the solvers iterate in (ed_apply_H on its twin).
+    Timed with HIP events on the launch stream."""
+    import torch
+    from paper_1004_3354_amd import ed
+    phys, nn, b, H, tset = setup(cfg, prec)
+    dt = torch.float64 if prec == ed.ED_FP64 else torch.float32
+    elem = 8 if prec == ed.ED_FP64 else 4
+    x = torch.empty(b.D, dtype=dt, device="cuda")
+    y = torch.empty_like(x)
+    ed.fill_random(x, 12345, 0)
+    out = {"D": b.D, "setup_s": round(tset, 3)}
+    for tag, HH in (("rank_order", H), ("grouped", H.grouped())):
+        if HH is None:
+            continue
+        wall, evt = timed_applies(HH, x, y, steps, warmup)
+        ms = evt / steps * 1e3
+        gbs = 2.0 * elem * b.D / (ms * 1e-3) / 1e9
+        out[tag] = {"ms_per_apply": round(ms, 5), "wall_ms": round(wall / steps * 1e3, 5), "gbps": round(gbs, 1),
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "schedule": ed.variant_name(HH.current_variant()),
+                    "schedule_id": HH.current_variant()}
+        log("N_s=%d %s %s H.v: %.4f ms, %.1f GB/s (%s)" % (phys["Ns"], "fp64" if prec == 0 else "fp32", tag, ms, gbs,
+                                                           out[tag]["schedule"]))
+    del x, y, H, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def lowest_leg(cfg, precs, k, opts_kw, seed_idx):
+    """E0 and the k lowest levels (with multiplicity) per precision from the
+    same start vector; time to the first level and to all k."""
+    import torch
+    from paper_1004_3354_amd import ed, workloads as wl
+    out = {}
+    for prec in precs:
+        phys, nn, b, H, tset = setup(cfg, prec)
+        dt = torch.float64 if prec == ed.ED_FP64 else torch.float32
+        v0 = torch.empty(b.D, dtype=dt, device="cuda")
+        ed.fill_random(v0, wl.start_vector_seed(seed_idx), 1)
+        kw = dict(opts_kw[prec]) if isinstance(opts_kw, dict) and prec in opts_kw else dict(opts_kw)
+        opts = ed.options(**kw)
+        evecs = torch.empty((k, b.D), dtype=dt, device="cuda")
+        ws = torch.empty(H.workspace_bytes(opts, k), dtype=torch.uint8, device="cuda")
+        (H.grouped() or H).apply(v0, evecs[0])          # tune outside the timed region
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, infos = H.lowest(1, v0, opts, ws=ws, evecs=evecs[:1], allow_noconv=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if k > 1:
+            ev, more = H.lowest_more(1, k, ev, v0, evecs, opts, ws=ws, allow_noconv=True)
+            infos = infos + more
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        key = "fp64" if prec == ed.ED_FP64 else "fp32_mixed"
+        out[key] = {"time_to_e0_s": round(t1 - t0, 4), "time_to_k_s": round(t2 - t0, 4), "E0": float(ev[0]),
+                    "levels": [float(e) for e in ev], "iters": [i["iters"] for i in infos],
+                    "residual": [i["residual"] for i in infos],
+                    "kato_temple_lower": [i["e_lower"] for i in infos], "converged": all(i["converged"] for i in infos),
+                    "max_basis": kw.get("max_basis"), "keep": kw.get("keep"), "setup_s": round(tset, 3)}
+        log("N_s=%d %s: E0 %.12f in %.3f s, %d levels in %.3f s" % (phys["Ns"], key, ev[0], t1 - t0, k, t2 - t0))
+        del ws, evecs, v0, H, b
+        torch.cuda.empty_cache()
+    if "fp64" in out and "fp32_mixed" in out:
+        a, c = out["fp64"], out["fp32_mixed"]
+        out["fp32_vs_fp64_rel"] = max(abs(x - y) / max(1.0, abs(x)) for x, y in zip(a["levels"], c["levels"]))
+        out["speedup_fp32_mixed_e0"] = round(a["time_to_e0_s"] / c["time_to_e0_s"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,15 +470,18 @@ def main():
     ap.add_argument("--no-e0", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ns18", action="store_true")
+    ap.add_argument("--no-ns16", action="store_true", help="skip the 4x4 Hubbard eigenvalue leg")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-green", action="store_true", help="skip the Green function at N_s=15")
     ap.add_argument("--no-thermal", action="store_true", help="skip the 300-level thermal pass at N_s=12")
     ap.add_argument("--e0-ns18", action="store_true", help=argparse.SUPPRESS)  # the default; kept for old scripts
-    ap.add_argument("--no-e0-ns18", action="store_true", help="skip time-to-E0 at N_s=18 (about two minutes)")
+    ap.add_argument("--no-e0-ns18", action="store_true", help="skip the eigenvalue legs at N_s=18")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="counter runs: tune, then K FP32 applies and K plain copies of x (known bytes)")
     ap.add_argument("--workload", choices=["ns15", "ns18"], default="ns15",
                     help="sector used by --pmc-pass")
+    ap.add_argument("--order", choices=["grouped", "rank"], default="grouped",
+                    help="basis order of the --pmc-pass apply")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sector is held by a single MI355X and no multi-GPU "
@@ -394,75 +494,28 @@ def main():
         pmc_pass(args)
         return
 
-    # ---- headline: FP32 H.v on the N_s = 15 sector
-    phys, nn, b, H, tset = setup(2, ed.ED_FP32)
-    D = b.D
-    x = torch.empty(D, dtype=torch.float32, device="cuda")
-    y = torch.empty_like(x)
-    ed.fill_random(x, 12345, 0)
-    log("N_s=15 FP32: D=%d setup %.3f s" % (D, tset))
-    wall, evt = timed_applies(H, x, y, args.steps, args.warmup)
-    variant = ed.variant_name(H.current_variant())
-    ms = wall / args.steps * 1e3
+    # ---- headline: FP32 H.v on the N_s = 15 sector in the grouped order the
+    # Lanczos solvers iterate in (the rank-order product beside it)
+    hv15 = apply_leg(2, ed.ED_FP32, args.steps, args.warmup)
+    head = hv15.get("grouped") or hv15["rank_order"]
+    D = hv15["D"]
     alg_bytes = 8.0 * D
-    value = alg_bytes * args.steps / wall / 1e9
-    kern_s = evt / args.steps
+    ms = head["wall_ms"]
+    value = alg_bytes / (ms * 1e-3) / 1e9
+    kern_s = head["ms_per_apply"] * 1e-3
     achieved = alg_bytes / kern_s / 1e9
-    log("FP32 H.v: %.4f ms/step (events %.4f ms), %.1f GB/s, schedule %s" % (ms, kern_s * 1e3, value, variant))
+    variant = head["schedule"]
     wl15 = "kanamori_Ns15_3orb_12bath_sector7_7"
-    traffic = traffic_from_profile(wl15, variant)
-    variant_id = H.current_variant()
-    del x, y, H, b
-    torch.cuda.empty_cache()
+    order = "grouped" if "grouped" in hv15 else "rank_order"
+    traffic = traffic_from_profile(wl15 + ("" if order == "rank_order" else "_grouped"), variant)
+    fp64 = apply_leg(2, ed.ED_FP64, max(5, args.steps // 2), 2)
 
-    # ---- FP64 H.v on the same sector
-    _, _, b64, H64, _ = setup(2, ed.ED_FP64)
-    x = torch.empty(D, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
-    ed.fill_random(x, 12345, 0)
-    w64, e64 = timed_applies(H64, x, y, max(5, args.steps // 2), 2)
-    fp64 = {"ms_per_apply": round(e64 / max(5, args.steps // 2) * 1e3, 4),
-            "gbps": round(16.0 * D * max(5, args.steps // 2) / e64 / 1e9, 1),
-            "schedule": ed.variant_name(H64.current_variant())}
-    fp64["frac"] = round(fp64["gbps"] / HBM_PEAK_GBS, 4)
-    del x, y, H64, b64
-    torch.cuda.empty_cache()
-
-    # ---- FP32 H.v on the N_s = 18 sector
     ns18 = None
-    if not args.no_ns18:
-        free, _ = torch.cuda.mem_get_info()
-        if free > 24e9:
-            _, _, b18, H18, t18 = setup(4, ed.ED_FP32)
-            x = torch.empty(b18.D, dtype=torch.float32, device="cuda")
-            y = torch.empty_like(x)
-            ed.fill_random(x, 12345, 0)
-            k18 = max(3, args.steps // 5)
-            w18, e18 = timed_applies(H18, x, y, k18, 2)
-            g18 = 8.0 * b18.D * k18 / e18 / 1e9
-            ns18 = {"workload": "kanamori_Ns18_3orb_15bath_sector9_9", "D": b18.D,
-                    "ms_per_apply": round(e18 / k18 * 1e3, 4), "gbps": round(g18, 1),
-                    "frac": round(g18 / HBM_PEAK_GBS, 4), "setup_s": round(t18, 3),
-                    "schedule": ed.variant_name(H18.current_variant()),
-                    "schedule_id": H18.current_variant(),
-                    "traffic": traffic_from_profile("kanamori_Ns18_3orb_15bath_sector9_9",
-                                                    ed.variant_name(H18.current_variant()))}
-            log("N_s=18 FP32 H.v: %.3f ms, %.1f GB/s" % (e18 / k18 * 1e3, g18))
-            del x, y, H18, b18
-            torch.cuda.empty_cache()
-            if torch.cuda.mem_get_info()[0] > 48e9:
-                _, _, b18, H18, _ = setup(4, ed.ED_FP64)
-                x = torch.empty(b18.D, dtype=torch.float64, device="cuda")
-                y = torch.empty_like(x)
-                ed.fill_random(x, 12345, 0)
-                w64, e64 = timed_applies(H18, x, y, k18, 2)
-                g64 = 16.0 * b18.D * k18 / e64 / 1e9
-                ns18["fp64"] = {"ms_per_apply": round(e64 / k18 * 1e3, 4), "gbps": round(g64, 1),
-                                "frac": round(g64 / HBM_PEAK_GBS, 4),
-                                "schedule": ed.variant_name(H18.current_variant())}
-                log("N_s=18 FP64 H.v: %.3f ms, %.1f GB/s" % (e64 / k18 * 1e3, g64))
-                del x, y, H18, b18
-                torch.cuda.empty_cache()
+    if not args.no_ns18 and torch.cuda.mem_get_info()[0] > 24e9:
+        ns18 = {"workload": "kanamori_Ns18_3orb_15bath_sector9_9",
+                "fp32": apply_leg(4, ed.ED_FP32, max(3, args.steps // 10), 1)}
+        if torch.cuda.mem_get_info()[0] > 48e9:
+            ns18["fp64"] = apply_leg(4, ed.ED_FP64, max(3, args.steps // 10), 1)
 
     # ---- time to E0, FP32-mixed vs FP64, same start vector and target
     e0 = e0_cgs2 = None
@@ -471,15 +524,27 @@ def main():
         e0 = time_to_e0(2, [ed.ED_FP32, ed.ED_FP64], max_basis=16, tol=1e-7, seed_idx=2, reorth=3, keep=8)
         # reference: two full Gram-Schmidt passes, restart from the Ritz vector
         e0_cgs2 = time_to_e0(2, [ed.ED_FP32, ed.ED_FP64], max_basis=50, tol=1e-7, seed_idx=2, reorth=2)
+    e0_16 = None
+    if not args.no_e0 and not args.no_ns16:
+        # 4x4 periodic Hubbard, U = 4, half filling: E0 and the 4 lowest levels
+        e0_16 = lowest_leg(1, [ed.ED_FP32, ed.ED_FP64], 4,
+                           {ed.ED_FP32: dict(tol=1e-7, reorth=3, keep=8, max_basis=24, max_iter=4000),
+                            ed.ED_FP64: dict(tol=1e-10, reorth=3, keep=8, max_basis=24, max_iter=4000)}, 1)
     e0_18 = None
     if not args.no_e0_ns18 and not args.no_e0 and not args.no_ns18:
         try:
-            e0_18 = time_to_e0(4, [ed.ED_FP32, ed.ED_FP64], max_basis={ed.ED_FP32: 16, ed.ED_FP64: 11},
-                               tol=1e-7, seed_idx=4, reorth=3, keep={ed.ED_FP32: 8, ed.ED_FP64: 5})
-        except torch.cuda.OutOfMemoryError as e:  # the FP64 basis needs ~230 GB of HBM
+            # FP32-mixed: E0, then the 3 lowest levels (16 stored vectors keeping 8);
+            # FP64: E0 (11 stored 18.9 GB vectors keeping 5)
+            e0_18 = lowest_leg(4, [ed.ED_FP32], 3, dict(tol=1e-7, reorth=3, keep=8, max_basis=16, max_iter=3000), 4)
+            e0_18.update(lowest_leg(4, [ed.ED_FP64], 1, dict(tol=1e-7, reorth=3, keep=5, max_basis=11, max_iter=3000),
+                                    4))
+            a, c = e0_18["fp64"], e0_18["fp32_mixed"]
+            e0_18["fp32_vs_fp64_rel"] = abs(a["E0"] - c["E0"]) / max(1.0, abs(a["E0"]))
+            e0_18["speedup_fp32_mixed_e0"] = round(a["time_to_e0_s"] / c["time_to_e0_s"], 3)
+        except torch.cuda.OutOfMemoryError as e:
             torch.cuda.empty_cache()
             e0_18 = {"skipped": "device memory: %s" % str(e).splitlines()[0]}
-            log("time-to-E0 N_s=18 skipped: out of device memory")
+            log("eigenvalue legs at N_s=18 skipped: out of device memory")
 
     green = None if args.no_green else green_bench()
     thermal = None if args.no_thermal else thermal_bench()
@@ -493,19 +558,22 @@ def main():
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp32", "data": "synthetic (seeded baths and SplitMix64 vectors)",
-        "config": {"workload": wl15, "Ns": 15, "sector": list(nn), "D": D,
-                   "step": "one FP32 matrix-free H.v (x, y resident in HBM)", "schedule": variant,
-                   "schedule_id": variant_id},
+        "config": {"workload": wl15, "Ns": 15, "sector": [7, 7], "D": D,
+                   "step": "one FP32 matrix-free H.v in the %s basis order%s (x, y resident in HBM)" %
+                           (order.replace("_", " "), " the Lanczos solvers iterate in" if order == "grouped" else ""),
+                   "schedule": variant, "schedule_id": head["schedule_id"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "%s (schedule %s)" % (schedule_kernels(variant), variant),
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": round(kern_s * 1e3, 5)},
         "cpu_baseline": cpu,
-        "fp64_hv": fp64,
-        "ns18_hv_fp32": ns18,
+        "hv_ns15_fp32": hv15,
+        "hv_ns15_fp64": fp64,
+        "hv_ns18": ns18,
         "time_to_e0_ns15": e0,
         "time_to_e0_ns15_cgs2": e0_cgs2,
+        "time_to_e0_ns16": e0_16,
         "time_to_e0_ns18": e0_18,
         "batched_ns12": batched,
         "green_ns15": green,

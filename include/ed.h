@@ -58,6 +58,7 @@ enum { ED_SPIN_FLIP = 1, ED_PAIR_HOP = 2, ED_UD_GENERAL = 3, ED_UU_GENERAL = 4, 
 
 typedef struct ed_basis_s *ed_basis_t;
 typedef struct ed_ham_s *ed_ham_t;
+typedef struct ed_levels_s *ed_levels_t;
 
 /* Version string of the library build. */
 const char *ed_version(void);
@@ -371,6 +372,47 @@ ed_status ed_green_cf(const double *alpha, const double *beta, int k, double nor
  * sum_i w[i] G_i(z), each G_i the zero-temperature one of level i.  EINVAL:
  * NULL arrays, n < 1, beta not in (0, inf), cutoff not in [0, 1), E non-finite. */
 ed_status ed_boltzmann_weights(const double *E, int n, double beta, double cutoff, double *w, int *kept);
+
+/* ---------------------------------------------------- lowest levels --------
+ * The K lowest levels over nsec sectors, counted with multiplicity: the
+ * thermal set the finite-temperature sum of Eq. 3 runs over (the paper's DMFT
+ * iteration at N_s = 12 needs the 300 lowest states, end of Section 3.2).
+ * Every sector's lowest level comes from one ed_lanczos_ground_batched run;
+ * then, while some sector with levels left has its highest computed level at
+ * or below the K-th lowest found so far, the sector whose highest computed
+ * level is lowest gets more (k -> k + max(2, k/4), at most min(D, kmax)) by
+ * ed_arnoldi_lowest_more on top of its converged vectors.  A sector's
+ * uncomputed levels lie above its highest computed one, so no level that could
+ * be among the K lowest is skipped.  Sector q's start vectors come from the
+ * SplitMix64 normal stream seed + q.  hs: nsec handles of one precision on one
+ * GPU; opts: the Lanczos options of every run (max_basis = 0 plans each run
+ * against the free device memory).  *out: a result handle that owns the
+ * eigenvectors it found (device memory the library allocates; ed_levels_free
+ * releases it).  Synchronous.  EINVAL: nsec < 1, K < 1, kmax outside
+ * [1, 200], NULL or mismatched handles. */
+ed_status ed_lowest_levels(int nsec, const ed_ham_t *hs, int K, int kmax, const ed_lanczos_opts *opts,
+                           uint64_t seed, ed_levels_t *out, void *stream);
+
+/* Counts of a result: levels at or below the threshold (the K-th lowest; more
+ * than K when a multiplet straddles it), calls of the eigensolver, sectors
+ * stopped at kmax while their highest level was still at or below the
+ * threshold (they may hold more levels), and the threshold itself (+inf when
+ * fewer than K levels exist).  Any output may be NULL. */
+ed_status ed_levels_info(ed_levels_t L, int *nlevels, int *calls, int *ncapped, double *threshold);
+
+/* The levels, ascending: energy, sector (index into hs) and index of the level
+ * within its sector (discovery order), HOST arrays of nlevels; any may be NULL. */
+ed_status ed_levels_get(ed_levels_t L, double *E, int32_t *sector, int32_t *index);
+
+/* Sector indices of the capped sectors, HOST [ncapped]. */
+ed_status ed_levels_capped(ed_levels_t L, int32_t *sectors);
+
+/* Copy the normalised eigenvector of level `index` of `sector` (rank order,
+ * D elements of the sector's precision) to DEVICE memory dst.  Asynchronous on
+ * stream.  EINVAL: no vector for that level. */
+ed_status ed_levels_vector(ed_levels_t L, int sector, int index, void *dst, void *stream);
+
+void ed_levels_free(ed_levels_t L);
 
 /* ------------------------------------------------------- sector batching ----
  * All sectors of one impurity problem at once (the paper's solver treats the

@@ -21,6 +21,7 @@
 // (consecutive row groups stay on one XCD so shared partner rows hit its L2).
 #include <algorithm>
 #include <climits>
+#include <map>
 #include <cmath>
 #include <cstdlib>
 #include <type_traits>
@@ -651,7 +652,10 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
                     const TA am = amps[ev[j] >> 20];
                     const int32_t l = t - w0;
                     if constexpr (GRP) {  // the window holds the whole component
-                        const RVt v = *reinterpret_cast<const RVt *>(xs + (uint32_t)l * R);
+                        // (a ragged chunk also computes columns outside the window,
+                        // whose results are discarded: keep their reads in the tile)
+                        const uint32_t lc = FULL ? (uint32_t)l : min((uint32_t)l, (uint32_t)(wl - 1));
+                        const RVt v = *reinterpret_cast<const RVt *>(xs + lc * R);
 #pragma unroll
                         for (int r = 0; r < R; ++r) acc[r][j] += am * (TA)rv_get<TX, R>(v, r);
                     } else if ((uint32_t)l < (uint32_t)wl) {
@@ -1044,6 +1048,216 @@ __global__ __launch_bounds__(BS) void k_upt(ApplyArgs<TX, TA> a) {
     }
 }
 
+// ------------------------------------------------- grouped tile kernel --
+// k_gtile: grouped basis order.  A workgroup takes one work item: R rows of
+// one up component and one window of whole down components (every down hop
+// stays in it), staged in LDS transposed (xs[l*R + r]: one LDS read returns a
+// column's values for all R rows, so each down-hop table entry serves R
+// outputs; small windows leave room for many rows).  Threads own four
+// consecutive columns of the window, whose own copy of the down hop table
+// holds window-local targets (no range test per hop).  H_up (x) 1 reads the
+// partner rows of the component from memory (the items of a tile run on one
+// XCD one after another, so those rows' window segments are L2 hits); the
+// four-fermion terms move both spins to other components and read memory.
+// UPX = false leaves H_up (x) 1 to a band pass.  Element offsets are 32-bit
+// (D < 2^32).
+template <typename TX, typename TA, int R, int BS, bool UPX>
+__global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
+    using RVt = typename RV<TX, R>::t;
+    using V = typename V4<TX>::t;
+    constexpr int UL = 32, XL = 16;
+    static_assert(BS % 64 == 0, "workgroups of whole waves");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    TX *xs = reinterpret_cast<TX *>(smem_raw);
+    TA *amps = reinterpret_cast<TA *>(smem_raw + (((size_t)R * a.wmax * sizeof(TX) + 15) & ~(size_t)15));
+    __shared__ int32_t u_src[R][UL];
+    __shared__ TA u_amp[R][UL];
+    __shared__ int32_t x_src[R][XL], x_tab[R][XL];
+    __shared__ TA x_amp[R][XL];
+    __shared__ TA usl[32], xtl[256];
+    const int4 it = a.items[blockIdx.x];
+    if (it.y <= 0) return;  // padding item: the whole workgroup leaves before any barrier
+    const uint32_t ddn = (uint32_t)a.ddn;
+    const int nr = it.y, wi = it.z;
+    const uint32_t w0 = (uint32_t)a.win[wi].x;
+    const int wl = a.win[wi].y;
+    for (int k = threadIdx.x; k < a.namp; k += BS) amps[k] = a.amp_tab[k];
+    if (a.umode == 2)
+        for (int k = threadIdx.x; k < 32; k += BS) usl[k] = a.usite[k];
+    if (a.koff)
+        for (int k = threadIdx.x; k < (1 << (2 * a.koff)); k += BS) xtl[k] = a.xtab[k];
+    uint32_t ur[R], su[R], cu[R];
+    TA eu[R];
+    int nu[R], nxl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool ok = r < nr;
+        const uint32_t u = (uint32_t)it.x + (ok ? r : 0);
+        ur[r] = u;
+        eu[r] = ok ? a.up_e[u] : (TA)0;
+        su[r] = ok ? a.up_st[u] : 0u;
+        cu[r] = ok ? a.up_c[u] : 0u;
+        const int32_t hb = a.up_off[u];
+        const int n = ok && UPX ? a.up_off[u + 1] - hb : 0;
+        nu[r] = (n + 3) & ~3;
+        for (int k = threadIdx.x; k < nu[r]; k += BS) {
+            u_src[r][k] = k < n ? a.up_tgt[hb + k] : (int32_t)u;
+            u_amp[r][k] = k < n ? a.up_sa[hb + k] : (TA)0;
+        }
+        const int32_t xb = a.xl_off[u];
+        nxl[r] = ok ? a.xl_off[u + 1] - xb : 0;
+        for (int k = threadIdx.x; k < nxl[r]; k += BS) {
+            x_src[r][k] = a.xl_src[xb + k];
+            x_tab[r][k] = a.xl_tab[xb + k];
+            x_amp[r][k] = a.xl_amp[xb + k];
+        }
+    }
+    // stage the tile, transposed
+    for (int cl = 4 * (int)threadIdx.x; cl < wl; cl += 4 * BS) {
+        TX v[R][4];
+        if (cl + 4 <= wl) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const V q = ld4(a.x + (ur[r] * ddn + w0 + (uint32_t)cl));
+                v[r][0] = q.x; v[r][1] = q.y; v[r][2] = q.z; v[r][3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[r][j] = cl + j < wl ? a.x[ur[r] * ddn + w0 + (uint32_t)(cl + j)] : (TX)0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (cl + j >= wl) break;
+            RVt o;
+            if constexpr (R == 1) o = v[0][j];
+            else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) o[r] = v[r][j];
+            }
+            *reinterpret_cast<RVt *>(xs + (uint32_t)(cl + j) * R) = o;
+        }
+    }
+    __syncthreads();
+    const int lane = (int)threadIdx.x & 63;
+    const int32_t gs0 = a.wsl_first[wi];
+    for (int cl = 4 * (int)threadIdx.x; cl < wl; cl += 4 * BS) {
+        const bool full = cl + 4 <= wl;
+        const uint32_t c = w0 + (uint32_t)cl;
+        TA edn[4];
+        uint32_t sd[4], cd[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool ok = cl + j < wl;
+            edn[j] = ok ? (TA)a.dn_e[c + j] : (TA)0;
+            sd[j] = ok ? a.dn_st[c + j] : 0u;
+            cd[j] = ok ? (uint32_t)a.dn_c[c + j] : 0u;
+        }
+        TA acc[R][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t l = (uint32_t)min(cl + j, wl - 1);
+            const RVt v = *reinterpret_cast<const RVt *>(xs + l * R);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                acc[r][j] = (eu[r] + edn[j] + cross_term_l(a, usl, xtl, su[r], sd[j], cu[r], cd[j])) *
+                            (TA)rv_get<TX, R>(v, r);
+        }
+        // 1 (x) H_dn: the window's table (padding entries have amplitude 0
+        // and a target inside the window)
+        {
+            const int32_t gs = gs0 + (cl >> 8);
+            const int32_t eb = a.wsl_off[gs];
+            const int32_t kk = (a.wsl_off[gs + 1] - eb) >> 6;
+            const uint4 *ep = a.wel4 + eb + lane;
+#pragma unroll 2
+            for (int32_t k = 0; k < kk; ++k) {
+                const uint4 e = ep[k * 64];
+                const uint32_t ev[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const TA am = amps[ev[j] >> 20];
+                    const RVt v = *reinterpret_cast<const RVt *>(xs + (ev[j] & 0xFFFFFu) * R);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r][j] += am * (TA)rv_get<TX, R>(v, r);
+                }
+            }
+        }
+        // H_up (x) 1: partner rows of the component, four 16-byte loads in flight
+        if constexpr (UPX) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (r >= nr) break;
+                for (int k = 0; k < nu[r]; k += 4) {
+                    if (full) {
+                        V v[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) v[i] = ld4(a.x + ((uint32_t)u_src[r][k + i] * ddn + c));
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const TA am = u_amp[r][k + i];
+                            acc[r][0] += am * (TA)v[i].x;
+                            acc[r][1] += am * (TA)v[i].y;
+                            acc[r][2] += am * (TA)v[i].z;
+                            acc[r][3] += am * (TA)v[i].w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const TA am = u_amp[r][k + i];
+                            const TX *row = a.x + (uint32_t)u_src[r][k + i] * ddn;
+#pragma unroll
+                            for (int j = 0; j < 4; ++j)
+                                if (cl + j < wl) acc[r][j] += am * (TA)row[c + j];
+                        }
+                    }
+                }
+            }
+        }
+        // four-fermion terms: partners in other components, from memory
+        if (a.nx) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (r >= nr) break;
+                for (int k = 0; k < nxl[r]; ++k) {
+                    const TX *src = a.x + (uint32_t)x_src[r][k] * ddn;
+                    const TA am = x_amp[r][k];
+                    const int32_t *mp = a.dn_mv + (uint32_t)x_tab[r][k] * ddn + c;
+                    int32_t m[4];
+                    if (full) {
+                        const int4 t4 = *reinterpret_cast<const int4 *>(mp);
+                        m[0] = t4.x; m[1] = t4.y; m[2] = t4.z; m[3] = t4.w;
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) m[j] = cl + j < wl ? mp[j] : -1;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (m[j] < 0) continue;
+                        const TA v = (TA)src[(uint32_t)m[j] >> 1];
+                        acc[r][j] += (m[j] & 1) ? -am * v : am * v;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r >= nr) break;
+            TX *yr = a.y + ur[r] * ddn;
+            if (full) {
+                V o;
+                o.x = (TX)acc[r][0]; o.y = (TX)acc[r][1]; o.z = (TX)acc[r][2]; o.w = (TX)acc[r][3];
+                st4<TX, true>(yr + c, o);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (cl + j < wl) yr[c + j] = (TX)acc[r][j];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------- variant table --
 // kind 0: single pass.  kind 1: two passes (row-local, then banded up spin).
 struct Variant {
@@ -1078,6 +1292,13 @@ static const Variant kVariants[] = {
     // + band pass of H_up (x) 1 over (up component, band) tiles
     {11, 2, 512, 128, "grp2_rt_r2_band128", 0, 32}, {11, 2, 512, 64, "grp2_rt_r2_band64", 0, 32},
     {11, 1, 512, 128, "grp2_rt_r1_band128", 0, 32},
+    // grouped order, lean tile kernel: R rows x a window of whole down
+    // components of about `band` states, per-window hop table
+    {12, 8, 256, 1024, "gt_r8_w1024"},      {12, 4, 256, 1024, "gt_r4_w1024"},
+    {12, 8, 256, 512, "gt_r8_w512"},        {12, 8, 256, 2048, "gt_r8_w2048"},
+    {12, 2, 512, 8192, "gt_r2_w8192"},      {12, 4, 512, 8192, "gt_r4_w8192"},
+    // the same as the row pass of two passes, with the band pass of H_up (x) 1
+    {13, 2, 512, 8192, "gt2_r2_w8192_band128", 0, 32}, {13, 8, 256, 1024, "gt2_r8_w1024_band128", 0, 32},
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static constexpr int64_t kDynBudget = 163840 - 8192;  // LDS left for the staged x block
@@ -1221,6 +1442,136 @@ static const int4 *items_for(ed_ham_s *h, int64_t key, const std::vector<int64_t
     h->item_counts.push_back((int64_t)out.size());
     *count = (int64_t)out.size();
     return m->as<int4>();
+}
+
+// Largest down component of a grouped handle.
+static int64_t max_down_component(const ed_ham_s *h) {
+    int64_t m = 0;
+    const std::vector<int32_t> &co = h->comp_off[1];
+    for (size_t k = 0; k + 1 < co.size(); ++k) m = std::max<int64_t>(m, co[k + 1] - co[k]);
+    return m;
+}
+
+// Work list over (up component, window) tiles, XCD-partitioned (items_for).
+static std::vector<int4> tile_items(const std::vector<int32_t> &co, const std::vector<int64_t> &cols, int rows) {
+    std::vector<int4> L;
+    std::vector<double> cost;
+    for (size_t A = 0; A + 1 < co.size(); ++A)
+        for (size_t w = 0; w < cols.size(); ++w)
+            for (int64_t u = co[A]; u < co[A + 1]; u += rows) {
+                const int nr = (int)std::min<int64_t>(rows, co[A + 1] - u);
+                L.push_back(make_int4((int)u, nr, (int)w, 0));
+                cost.push_back((double)nr * (double)cols[w]);
+            }
+    double total = 0.0;
+    for (double c : cost) total += c;
+    constexpr int kX = 8;
+    std::vector<std::vector<int4>> run(kX);
+    double acc = 0.0;
+    for (size_t i = 0; i < L.size(); ++i) {
+        const int x = std::min(kX - 1, (int)(acc / std::max(total, 1.0) * kX));
+        run[x].push_back(L[i]);
+        acc += cost[i];
+    }
+    size_t len = 1;
+    for (auto &r : run) len = std::max(len, r.size());
+    std::vector<int4> out(len * kX, make_int4(0, 0, 0, 0));
+    for (int x = 0; x < kX; ++x)
+        for (size_t i = 0; i < run[x].size(); ++i) out[x + kX * i] = run[x][i];
+    return out;
+}
+
+// Plan of k_gtile with R rows per tile and windows of about `wtarget` states
+// (consecutive down components merged while they fit; a larger component is a
+// window of its own).  Cached on the handle.
+static const TilePlan *tile_plan(ed_ham_s *h, int R, int64_t wtarget) {
+    const int64_t key = (int64_t)R << 32 | wtarget;
+    for (auto *t : h->tplans)
+        if (t->key == key) return t;
+    const SpinTab &dn = h->sp[1];
+    const int64_t dim = dn.dim;
+    std::vector<int32_t> off((size_t)dim + 1), tgt((size_t)std::max<int64_t>(dn.nnz, 1));
+    std::vector<double> sa((size_t)std::max<int64_t>(dn.nnz, 1));
+    ED_HIP(hipMemcpy(off.data(), dn.off.p, off.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (dn.nnz > 0) {
+        ED_HIP(hipMemcpy(tgt.data(), dn.tgt.p, (size_t)dn.nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+        ED_HIP(hipMemcpy(sa.data(), dn.sa64.p, (size_t)dn.nnz * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    // windows: whole components
+    std::vector<int2> win;
+    const std::vector<int32_t> &co = h->comp_off[1];
+    int64_t cs = 0, cl = 0;
+    for (size_t k = 0; k + 1 < co.size(); ++k) {
+        const int64_t n = co[k + 1] - co[k];
+        if (cl > 0 && cl + n > wtarget) {
+            win.push_back(make_int2((int)cs, (int)cl));
+            cs = co[k];
+            cl = 0;
+        }
+        cl += n;
+    }
+    if (cl > 0) win.push_back(make_int2((int)cs, (int)cl));
+    // distinct signed amplitudes (index 0 is the zero of the padding)
+    std::vector<double> vals{0.0};
+    std::map<double, int> idx;
+    idx[0.0] = 0;
+    for (int64_t e = 0; e < dn.nnz; ++e)
+        if (!idx.count(sa[e])) {
+            if (vals.size() >= 4095) fail(ED_EUNSUPPORTED, "down hop table has more than 4094 distinct amplitudes");
+            idx.emplace(sa[e], (int)vals.size());
+            vals.push_back(sa[e]);
+        }
+    // per-window slices of 256 states, lane l holding states 4l..4l+3
+    std::vector<int32_t> first, soff;
+    std::vector<uint32_t> ent;
+    int wmax = 0;
+    for (const int2 &w : win) {
+        wmax = std::max(wmax, w.y);
+        first.push_back((int32_t)soff.size());
+        for (int64_t s0 = 0; s0 < w.y; s0 += 256) {
+            int kk = 0;
+            for (int64_t q = w.x + s0; q < std::min<int64_t>(w.x + w.y, w.x + s0 + 256); ++q)
+                kk = std::max(kk, off[q + 1] - off[q]);
+            soff.push_back((int32_t)(ent.size() / 4));
+            for (int k = 0; k < kk; ++k)
+                for (int l = 0; l < 256; ++l) {
+                    const int64_t q = w.x + s0 + l;
+                    uint32_t v = q < w.x + w.y ? (uint32_t)(q - w.x) : 0u;
+                    if (q < w.x + w.y && k < off[q + 1] - off[q]) {
+                        const int64_t e = off[q] + k, t = (int64_t)tgt[e] - w.x;
+                        if (t < 0 || t >= w.y) fail(ED_EDEVICE, "tile plan: a down hop leaves its component");
+                        v = (uint32_t)t | ((uint32_t)idx.at(sa[e]) << 20);
+                    }
+                    ent.push_back(v);
+                }
+        }
+    }
+    first.push_back((int32_t)soff.size());
+    soff.push_back((int32_t)(ent.size() / 4));
+    if (ent.empty()) ent.assign(4, 0u);
+    std::vector<int64_t> cols;
+    for (const int2 &w : win) cols.push_back(w.y);
+    const std::vector<int4> items = tile_items(h->comp_off[0], cols, R);
+    TilePlan *t = new TilePlan();
+    try {
+        t->key = key;
+        t->nwin = (int)win.size();
+        t->wmax = wmax;
+        t->namp = (int)vals.size();
+        t->nitems = (int64_t)items.size();
+        upload(t->win, win);
+        upload(t->wsl_first, first);
+        upload(t->wsl_off, soff);
+        upload(t->wel4, ent);
+        upload(t->amp64, vals);
+        upload(t->amp32, std::vector<float>(vals.begin(), vals.end()));
+        upload(t->items, items);
+    } catch (...) {
+        delete t;
+        throw;
+    }
+    h->tplans.push_back(t);
+    return t;
 }
 
 template <typename TX, typename TA>
@@ -1436,6 +1787,25 @@ static void launch_upb(const ApplyArgs<TX, TA> &a, int64_t band, int rw, hipStre
     ED_LAUNCH_CHECK();
 }
 
+template <typename TX, typename TA, int R, int BS, bool UPX = true>
+static void launch_gtile(ed_ham_s *h, ApplyArgs<TX, TA> a, int64_t wtarget, hipStream_t s) {
+    const TilePlan *t = tile_plan(h, R, wtarget);
+    a.win = t->win.as<int2>();
+    a.nwin = t->nwin;
+    a.wmax = t->wmax;
+    a.items = t->items.as<int4>();
+    a.wsl_first = t->wsl_first.as<int32_t>();
+    a.wsl_off = t->wsl_off.as<int32_t>();
+    a.wel4 = t->wel4.as<uint4>();
+    a.namp = t->namp;
+    a.amp_tab = sizeof(TA) == 8 ? (const TA *)t->amp64.p : (const TA *)t->amp32.p;
+    const size_t shm = (((size_t)R * (size_t)t->wmax * sizeof(TX) + 15) & ~(size_t)15) + (size_t)t->namp * sizeof(TA);
+    auto kern = k_gtile<TX, TA, R, BS, UPX>;
+    allow_lds(kern);
+    kern<<<(unsigned)t->nitems, BS, shm, s>>>(a);
+    ED_LAUNCH_CHECK();
+}
+
 // register-tile sizes of the column-stationary kernels
 static int cs_kmax(const ed_ham_s *h) {
     const int m = std::max(h->sp[0].max_hops, h->sp[1].max_hops);
@@ -1522,6 +1892,20 @@ static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipSt
             launch_rt<TX, TA, 1, 512, false>(h, a, s, 0, true);
             launch_upt<TX, TA>(h, a, V.band, V.rw, s);
             break;
+        case 23: launch_gtile<TX, TA, 8, 256>(h, a, 1024, s); break;
+        case 24: launch_gtile<TX, TA, 4, 256>(h, a, 1024, s); break;
+        case 25: launch_gtile<TX, TA, 8, 256>(h, a, 512, s); break;
+        case 26: launch_gtile<TX, TA, 8, 256>(h, a, 2048, s); break;
+        case 27: launch_gtile<TX, TA, 2, 512>(h, a, 8192, s); break;
+        case 28: launch_gtile<TX, TA, 4, 512>(h, a, 8192, s); break;
+        case 29:
+            launch_gtile<TX, TA, 2, 512, false>(h, a, 8192, s);
+            launch_upt<TX, TA>(h, a, 128, V.rw, s);
+            break;
+        case 30:
+            launch_gtile<TX, TA, 8, 256, false>(h, a, 1024, s);
+            launch_upt<TX, TA>(h, a, 128, V.rw, s);
+            break;
         default: fail(ED_EINVAL, "bad apply variant %d", v);
     }
 }
@@ -1536,6 +1920,15 @@ static bool variant_fits(const ed_ham_s *h, int v, size_t elem) {
     if (V.kind == 8 && (h->sp[0].nnz == 0 || cs_kmax(h) == 0 || cs_nmv(h) < 0 || (h->nx > 0 && cs_xmax(h) == 0)))
         return false;
     if (V.kind == 8 && V.BS > 512 && cs_kmax(h) > 16) return false;
+    if (V.kind == 12 || V.kind == 13) {
+        // grouped tile kernel: every down component whole in a window that fits LDS
+        if (!h->grouped || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->koff > 4 || h->D >= ((int64_t)1 << 32) ||
+            h->ddn >= (1 << 20))
+            return false;
+        const int64_t wmax = std::max<int64_t>(max_down_component(h), std::min<int64_t>(V.band, h->ddn));
+        if ((int64_t)V.R * wmax * (int64_t)elem + 4096 * (int64_t)elem + 16 > kDynBudget) return false;
+        if (max_down_component(h) > 2 * V.band) return false;
+    }
     if (V.kind == 10 || V.kind == 11) {
         if (!h->grouped || !h->sp[1].pk_ok || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->koff > 4 ||
             h->D >= ((int64_t)1 << 32))

@@ -114,6 +114,22 @@ struct ed_basis_s {
 
 namespace ed {
 
+// Plan of the grouped-order tile kernel for one (rows per tile, window size)
+// choice: windows of whole down components, a per-window copy of the down hop
+// table with window-local targets, and the tile-major work list.
+struct TilePlan {
+    int64_t key = 0;
+    int nwin = 0, wmax = 0, namp = 0;
+    int64_t nitems = 0;
+    DevMem win;        // int2 [nwin]: (first position, length)
+    DevMem wsl_first;  // int32 [nwin + 1]: first slice of each window
+    DevMem wsl_off;    // int32 [nslices + 1]: slice offsets in uint4 units
+    DevMem wel4;       // uint4 [(slice, k, lane)]: four consecutive states per lane,
+                       // window-local target (bits 0..19) | amplitude index (20..31)
+    DevMem amp64, amp32;
+    DevMem items;      // int4 [nitems]
+};
+
 // ------------------------------------------------------------ spin tables --
 // Tables of one spin species.  Arrays suffixed 64/32 hold FP64 / FP32 copies.
 struct SpinTab {
@@ -213,9 +229,11 @@ struct ed_ham_s {
     // (key, device int4 list of (first row, rows, window or band, 0), count)
     std::vector<std::pair<int64_t, ed::DevMem *>> items;
     std::vector<int64_t> item_counts;
+    std::vector<ed::TilePlan *> tplans;
     ~ed_ham_s() {
         for (auto &w : windows) delete w.second;
         for (auto &w : items) delete w.second;
+        for (auto *t : tplans) delete t;
         delete twin;
     }
 };
@@ -271,6 +289,9 @@ struct ApplyArgs {
     // optional work list (grouped schedules): workgroup b takes items[b] =
     // (first row, rows, window or band, 0); rows = 0 is an empty item
     const int4 *items;
+    // grouped tile kernel: per-window slices of the down hop table
+    const int32_t *wsl_first, *wsl_off;
+    const uint4 *wel4;
 };
 
 // Build all tables of a Hamiltonian handle (tables.hip).

@@ -8,4 +8,5 @@
 #include "lanczos.hip"
 #include "batched.hip"
 #include "green.hip"
+#include "levels.hip"
 #include "noalloc.hip"

@@ -164,6 +164,169 @@ __global__ __launch_bounds__(kRedBS) void k_lincomb(const TX *const *vecs, const
     }
 }
 
+// Vector forms of the three kernels above for the single-sector solver: each
+// thread takes four consecutive elements per iteration (one 16-byte load per
+// FP32 vector, two per FP64 vector) and keeps G vectors' loads in flight.
+// Block ranges start at multiples of 64 elements and slots are 256-byte
+// aligned, so every group of four inside a block is aligned; a block's ragged
+// end is done element by element.  Same partial layout and fixed reduction
+// order per block as the scalar forms.
+// (vectors declared with element alignment only: a locked vector inside a
+// caller's [k][D] array starts at a multiple of D elements, and gfx950 global
+// memory accepts 16-byte accesses at element alignment)
+typedef float f4e __attribute__((ext_vector_type(4), aligned(4)));
+typedef double d2e __attribute__((ext_vector_type(2), aligned(8)));
+template <typename TX>
+struct Q4 {
+    TX v[4];
+};
+template <typename TX>
+__device__ __forceinline__ Q4<TX> load4(const TX *p) {
+    Q4<TX> q;
+    if constexpr (sizeof(TX) == 4) {
+        const f4e t = *reinterpret_cast<const f4e *>(p);
+        q.v[0] = t.x; q.v[1] = t.y; q.v[2] = t.z; q.v[3] = t.w;
+    } else {
+        const d2e a = *reinterpret_cast<const d2e *>(p), b = *reinterpret_cast<const d2e *>(p + 2);
+        q.v[0] = a.x; q.v[1] = a.y; q.v[2] = b.x; q.v[3] = b.y;
+    }
+    return q;
+}
+template <typename TX>
+__device__ __forceinline__ void store4(TX *p, const Q4<TX> &q) {
+    if constexpr (sizeof(TX) == 4) {
+        f4e t;
+        t.x = q.v[0]; t.y = q.v[1]; t.z = q.v[2]; t.w = q.v[3];
+        *reinterpret_cast<f4e *>(p) = t;
+    } else {
+        d2e a, b;
+        a.x = q.v[0]; a.y = q.v[1]; b.x = q.v[2]; b.y = q.v[3];
+        *reinterpret_cast<d2e *>(p) = a;
+        *reinterpret_cast<d2e *>(p + 2) = b;
+    }
+}
+
+// partials[v * nblk + blk] = sum S_v Y (and with Z, when z != NULL, at
+// partials[(nvec + v) * nblk + blk])
+template <typename TX, int G, bool TWO>
+__global__ __launch_bounds__(kRedBS) void k_multidot_v4(const TX *const *vecs, int nvec, const TX *y, const TX *z,
+                                                        int64_t n, double *partials) {
+    __shared__ double red[kRedBS / 64];
+    const int nblk = gridDim.x, blk = blockIdx.x;
+    int64_t a, b;
+    block_range(n, nblk, blk, a, b);
+    for (int g0 = 0; g0 < nvec; g0 += G) {
+        double ay[G], az[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) ay[i] = az[i] = 0.0;
+        const TX *vp[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) vp[i] = vecs[(g0 + i < nvec) ? g0 + i : g0];
+        int64_t k = a + 4 * (int64_t)threadIdx.x;
+        for (; k + 4 <= b; k += 4 * kRedBS) {
+            const Q4<TX> yv = load4(y + k);
+            Q4<TX> zv;
+            if constexpr (TWO) zv = load4(z + k);
+            Q4<TX> sv[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i)
+                if (g0 + i < nvec) sv[i] = load4(vp[i] + k);
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                if (g0 + i >= nvec) break;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    ay[i] += (double)sv[i].v[e] * (double)yv.v[e];
+                    if constexpr (TWO) az[i] += (double)sv[i].v[e] * (double)zv.v[e];
+                }
+            }
+        }
+        for (int64_t e = k; e < b && e < k + 4; ++e) {  // ragged end of the block
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                if (g0 + i >= nvec) break;
+                ay[i] += (double)vp[i][e] * (double)y[e];
+                if constexpr (TWO) az[i] += (double)vp[i][e] * (double)z[e];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (g0 + i >= nvec) break;
+            const double sy = block_sum_any<kRedBS>(ay[i], red);
+            if (threadIdx.x == 0) partials[(int64_t)(g0 + i) * nblk + blk] = sy;
+            if constexpr (TWO) {
+                const double sz = block_sum_any<kRedBS>(az[i], red);
+                if (threadIdx.x == 0) partials[(int64_t)(nvec + g0 + i) * nblk + blk] = sz;
+            }
+        }
+    }
+}
+
+// Y = post * ((assign ? 0 : Y) - sum_i coef[i] S_i) as k_lincomb, four
+// elements per thread, four vectors' loads in flight.
+template <typename TX>
+__global__ __launch_bounds__(kRedBS) void k_lincomb_v4(const TX *const *vecs, const double *coef, int nvec, TX *y,
+                                                       int64_t n, int assign, double sign, double *norm_part,
+                                                       const double *post_sig2) {
+    __shared__ double c[kMaxVec];
+    __shared__ const TX *p[kMaxVec];
+    __shared__ double red[kRedBS / 64];
+    for (int i = threadIdx.x; i < nvec; i += kRedBS) {
+        c[i] = sign * coef[i];
+        p[i] = vecs[i];
+    }
+    __syncthreads();
+    int64_t a, b;
+    block_range(n, gridDim.x, blockIdx.x, a, b);
+    const double post = post_sig2 ? sqrt(*post_sig2) : 1.0;
+    double nrm = 0.0;
+    int64_t k = a + 4 * (int64_t)threadIdx.x;
+    for (; k + 4 <= b; k += 4 * kRedBS) {
+        double v[4];
+        if (assign) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = 0.0;
+        } else {
+            const Q4<TX> q = load4(y + k);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (double)q.v[e];
+        }
+        int i = 0;
+        for (; i + 4 <= nvec; i += 4) {
+            Q4<TX> s4[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) s4[t] = load4(p[i + t] + k);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] -= c[i + t] * (double)s4[t].v[e];
+        }
+        for (; i < nvec; ++i) {
+            const Q4<TX> q = load4(p[i] + k);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] -= c[i] * (double)q.v[e];
+        }
+        Q4<TX> o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            o.v[e] = (TX)(post * v[e]);
+            nrm += (double)o.v[e] * (double)o.v[e];
+        }
+        store4(y + k, o);
+    }
+    for (int64_t e = k; e < b && e < k + 4; ++e) {
+        double v = assign ? 0.0 : (double)y[e];
+        for (int i = 0; i < nvec; ++i) v -= c[i] * (double)p[i][e];
+        const TX st = (TX)(post * v);
+        y[e] = st;
+        nrm += (double)st * (double)st;
+    }
+    if (norm_part) {
+        const double sm = block_sum_any<kRedBS>(nrm, red);
+        if (threadIdx.x == 0) norm_part[blockIdx.x] = sm;
+    }
+}
+
 // Implicit restart, in place: out_o[n] = sum_i C[i * nout + o] in_i[n] for
 // o < nout, where out_o is the storage of in_o (each element's inputs are read
 // by the thread that writes its outputs, before it writes them).  Norm partials
@@ -692,14 +855,14 @@ struct Solver {
     template <typename TX>
     void multidot(int vbeg, int nvec, const void *y) {
         const TX *const *vecs = (const TX *const *)(w.vp + vbeg);
-        k_multidot<TX, 8><<<w.nblk, kRedBS, 0, s>>>(vecs, nvec, (const TX *)y, h->D, w.partials);
+        k_multidot_v4<TX, 8, false><<<w.nblk, kRedBS, 0, s>>>(vecs, nvec, (const TX *)y, nullptr, h->D, w.partials);
         ED_LAUNCH_CHECK();
     }
     template <typename TX>
     void lincomb(int vbeg, const double *coef, int nvec, void *y, int assign, double sign, double *normp,
                  const double *post) {
         const TX *const *vecs = (const TX *const *)(w.vp + vbeg);
-        k_lincomb<TX><<<w.nblk, kRedBS, 0, s>>>(vecs, coef, nvec, (TX *)y, h->D, assign, sign, normp, post);
+        k_lincomb_v4<TX><<<w.nblk, kRedBS, 0, s>>>(vecs, coef, nvec, (TX *)y, h->D, assign, sign, normp, post);
         ED_LAUNCH_CHECK();
     }
     void dots(int vbeg, int nvec, const void *y, double *alpha, int jrel) {
@@ -711,11 +874,13 @@ struct Solver {
     // both projections of one step from a single read of the basis (reorth = 3)
     void dots_gram(int nvec, const void *y, const void *z, double *alpha) {
         if (h->prec == ED_FP64)
-            k_multidot2<double, 16><<<w.nblk, kRedBS, 0, s>>>((const double *const *)w.vp, nvec, (const double *)y,
-                                                             (const double *)z, h->D, w.partials);
+            k_multidot_v4<double, 8, true><<<w.nblk, kRedBS, 0, s>>>((const double *const *)w.vp, nvec,
+                                                                    (const double *)y, (const double *)z, h->D,
+                                                                    w.partials);
         else
-            k_multidot2<float, 16><<<w.nblk, kRedBS, 0, s>>>((const float *const *)w.vp, nvec, (const float *)y,
-                                                            (const float *)z, h->D, w.partials);
+            k_multidot_v4<float, 8, true><<<w.nblk, kRedBS, 0, s>>>((const float *const *)w.vp, nvec,
+                                                                   (const float *)y, (const float *)z, h->D,
+                                                                   w.partials);
         ED_LAUNCH_CHECK();
         k_finalize_gram<<<1, 256, 0, s>>>(w.partials, nvec, w.nblk, w.sig2, w.gram, w.m + 1, w.gamma, alpha);
         ED_LAUNCH_CHECK();

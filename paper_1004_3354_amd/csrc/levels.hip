@@ -1,0 +1,214 @@
+// The K lowest levels over a set of sectors, counted with multiplicity: the
+// thermal set that the finite-temperature sum of Eq. 3 runs over.  The paper's
+// DMFT iteration at N_s = 12 needs the 300 lowest eigenstates of the impurity
+// Hamiltonian (its comparison at the end of Section 3.2).
+//
+// Search: every sector's lowest level comes from one batched ground-state run;
+// then, as long as some sector that still has levels left has its highest
+// computed level at or below the K-th lowest level found so far, the sector
+// whose highest computed level is lowest gets more levels (restarted Lanczos
+// with explicit deflation against the converged vectors, continuing from
+// them).  A sector's uncomputed levels all lie above its highest computed one,
+// so no level that could belong to the K lowest is skipped.  The vectors of
+// the levels found stay in device memory owned by the result handle.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "ed_internal.h"
+
+struct ed_levels_s {
+    int device = 0;
+    std::vector<ed_ham_s *> hs;
+    std::vector<std::vector<double>> energies;  // per sector, in discovery order (ascending up to rounding)
+    std::vector<ed::DevMem *> vecs;             // per sector: [nvec][D] eigenvectors in rank order
+    std::vector<int> nvec;
+    struct Level {
+        double E;
+        int s, i;
+    };
+    std::vector<Level> levels;
+    std::vector<int> capped;
+    int calls = 0;
+    double threshold = INFINITY;
+    ~ed_levels_s() {
+        for (auto *v : vecs) delete v;
+    }
+};
+
+namespace ed {
+
+static double kth_lowest(const std::vector<std::vector<double>> &en, int K) {
+    std::vector<double> all;
+    for (auto &e : en) all.insert(all.end(), e.begin(), e.end());
+    if ((int)all.size() < K) return INFINITY;
+    std::nth_element(all.begin(), all.begin() + (K - 1), all.end());
+    return all[K - 1];
+}
+
+static double highest(const std::vector<double> &e) { return *std::max_element(e.begin(), e.end()); }
+
+static void lowest_levels(ed_levels_s *L, int nsec, const ed_ham_t *hs, int K, int kmax,
+                          const ed_lanczos_opts *opts, uint64_t seed, hipStream_t s) {
+    L->hs.assign(hs, hs + nsec);
+    L->energies.assign(nsec, {});
+    L->vecs.assign(nsec, nullptr);
+    L->nvec.assign(nsec, 0);
+    // every sector's lowest level from one batched run
+    {
+        size_t nb = 0;
+        ed_status st = ed_batched_workspace_bytes(nsec, hs, opts, &nb);
+        if (st != ED_OK) fail(st, "%s", ed_last_error());
+        DevMem bws;
+        bws.alloc(nb);
+        std::vector<double> e0((size_t)nsec);
+        st = ed_lanczos_ground_batched(nsec, hs, opts, nullptr, seed, bws.p, nb, e0.data(), nullptr, s);
+        if (st != ED_OK && st != ED_ENOCONV) fail(st, "%s", ed_last_error());
+        for (int q = 0; q < nsec; ++q) L->energies[q] = {e0[q]};
+    }
+    int64_t dmax = 1;
+    for (auto *h : L->hs) dmax = std::max(dmax, h->D);
+    const size_t elem = L->hs[0]->prec == ED_FP64 ? 8 : 4;
+    DevMem v0, ws;
+    v0.alloc((size_t)dmax * elem);
+    auto extend = [&](int q, int k) {
+        ed_ham_s *h = L->hs[q];
+        const int k0 = L->nvec[q];
+        DevMem *ev = new DevMem();
+        try {
+            ev->alloc((size_t)k * (size_t)h->D * elem);
+            if (k0 > 0)
+                ED_HIP(hipMemcpyAsync(ev->p, L->vecs[q]->p, (size_t)k0 * (size_t)h->D * elem, hipMemcpyDeviceToDevice,
+                                      s));
+            k_fill<<<grid_for(h->D, 256, 1 << 16), 256, 0, s>>>(v0.p, h->D, seed + (uint64_t)q, 1,
+                                                               h->prec == ED_FP32 ? 1 : 0);
+            ED_LAUNCH_CHECK();
+            const ed_lanczos_opts o = resolve(h, opts, k, false, device_budget());
+            const size_t need = ws_needed(h, o, k, false);
+            if (ws.bytes < need) ws.alloc(need);
+            std::vector<double> ev_h((size_t)k, 0.0);
+            for (int i = 0; i < k0; ++i) ev_h[i] = L->energies[q][i];
+            const ed_status st = solve(h, k, &o, v0.p, ws.p, ws.bytes, ev_h.data(), ev->p, nullptr, s, k0);
+            if (st != ED_OK && st != ED_ENOCONV)
+                fail(st, "sector %d (D = %lld), %d levels: %s", q, (long long)h->D, k, ed_last_error());
+            L->energies[q].assign(ev_h.begin(), ev_h.end());
+        } catch (...) {
+            delete ev;
+            throw;
+        }
+        delete L->vecs[q];
+        L->vecs[q] = ev;
+        L->nvec[q] = k;
+        ++L->calls;
+    };
+    std::vector<bool> capped((size_t)nsec, false);
+    while (true) {
+        const double T = kth_lowest(L->energies, K);
+        int best = -1;
+        for (int q = 0; q < nsec; ++q) {
+            const int have = (int)L->energies[q].size();
+            const int64_t lim = std::min<int64_t>(L->hs[q]->D, kmax);
+            if (highest(L->energies[q]) > T) continue;
+            if (have >= lim) {
+                if (have < L->hs[q]->D) capped[q] = true;
+                continue;
+            }
+            if (best < 0 || highest(L->energies[q]) < highest(L->energies[best])) best = q;
+        }
+        if (best < 0) break;
+        const int k = L->nvec[best];
+        extend(best, (int)std::min<int64_t>(std::min<int64_t>(L->hs[best]->D, kmax), k + std::max(2, k / 4)));
+    }
+    L->threshold = kth_lowest(L->energies, K);
+    for (int q = 0; q < nsec; ++q)  // one-level sectors: the energy is known, the vector not yet
+        if (L->nvec[q] == 0 && L->energies[q][0] <= L->threshold) extend(q, 1);
+    for (int q = 0; q < nsec; ++q) {
+        if (capped[q]) L->capped.push_back(q);
+        for (int i = 0; i < (int)L->energies[q].size(); ++i)
+            if (L->energies[q][i] <= L->threshold) L->levels.push_back({L->energies[q][i], q, i});
+    }
+    std::sort(L->levels.begin(), L->levels.end(), [](const ed_levels_s::Level &a, const ed_levels_s::Level &b) {
+        return a.E < b.E || (a.E == b.E && (a.s < b.s || (a.s == b.s && a.i < b.i)));
+    });
+    ED_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace ed
+
+using namespace ed;
+
+extern "C" ed_status ed_lowest_levels(int nsec, const ed_ham_t *hs, int K, int kmax, const ed_lanczos_opts *opts,
+                                      uint64_t seed, ed_levels_t *out, void *stream) {
+    return guard([&] {
+        if (!out) fail(ED_EINVAL, "ed_lowest_levels: out is NULL");
+        *out = nullptr;
+        if (nsec < 1 || !hs) fail(ED_EINVAL, "ed_lowest_levels: no sectors");
+        if (K < 1 || kmax < 1 || kmax > 200) fail(ED_EINVAL, "ed_lowest_levels: need K >= 1 and 1 <= kmax <= 200");
+        for (int q = 0; q < nsec; ++q) {
+            if (!hs[q]) fail(ED_EINVAL, "ed_lowest_levels: NULL handle %d", q);
+            if (hs[q]->prec != hs[0]->prec || hs[q]->device != hs[0]->device)
+                fail(ED_EINVAL, "ed_lowest_levels: sectors must share one precision and one GPU");
+        }
+        DeviceGuard g(hs[0]->device);
+        ed_levels_s *L = new ed_levels_s();
+        try {
+            L->device = hs[0]->device;
+            lowest_levels(L, nsec, hs, K, kmax, opts, seed, (hipStream_t)stream);
+        } catch (...) {
+            delete L;
+            throw;
+        }
+        *out = L;
+    });
+}
+
+extern "C" ed_status ed_levels_info(ed_levels_t L, int *nlevels, int *calls, int *ncapped, double *threshold) {
+    return guard([&] {
+        if (!L) fail(ED_EINVAL, "ed_levels_info: NULL handle");
+        if (nlevels) *nlevels = (int)L->levels.size();
+        if (calls) *calls = L->calls;
+        if (ncapped) *ncapped = (int)L->capped.size();
+        if (threshold) *threshold = L->threshold;
+    });
+}
+
+extern "C" ed_status ed_levels_get(ed_levels_t L, double *E, int32_t *sector, int32_t *index) {
+    return guard([&] {
+        if (!L) fail(ED_EINVAL, "ed_levels_get: NULL handle");
+        for (size_t i = 0; i < L->levels.size(); ++i) {
+            if (E) E[i] = L->levels[i].E;
+            if (sector) sector[i] = L->levels[i].s;
+            if (index) index[i] = L->levels[i].i;
+        }
+    });
+}
+
+extern "C" ed_status ed_levels_capped(ed_levels_t L, int32_t *sectors) {
+    return guard([&] {
+        if (!L || !sectors) fail(ED_EINVAL, "ed_levels_capped: NULL argument");
+        for (size_t i = 0; i < L->capped.size(); ++i) sectors[i] = L->capped[i];
+    });
+}
+
+extern "C" ed_status ed_levels_vector(ed_levels_t L, int sector, int index, void *dst, void *stream) {
+    return guard([&] {
+        if (!L || !dst) fail(ED_EINVAL, "ed_levels_vector: NULL argument");
+        if (sector < 0 || sector >= (int)L->hs.size() || index < 0 || index >= L->nvec[sector])
+            fail(ED_EINVAL, "ed_levels_vector: no vector for level %d of sector %d", index, sector);
+        DeviceGuard g(L->device);
+        const ed_ham_s *h = L->hs[sector];
+        const size_t bytes = (size_t)h->D * (h->prec == ED_FP64 ? 8 : 4);
+        ED_HIP(hipMemcpyAsync(dst, (char *)L->vecs[sector]->p + (size_t)index * bytes, bytes, hipMemcpyDeviceToDevice,
+                              (hipStream_t)stream));
+    });
+}
+
+extern "C" void ed_levels_free(ed_levels_t L) {
+    if (!L) return;
+    try {
+        DeviceGuard g(L->device);
+        (void)hipDeviceSynchronize();
+        delete L;
+    } catch (...) {
+    }
+}

@@ -113,6 +113,14 @@ _sig("ed_green_cf", ctypes.c_int, [_p, _p, ctypes.c_int, ctypes.c_double, ctypes
                                    ctypes.c_double, _p, _p, ctypes.c_int, _p, _p])
 _sig("ed_boltzmann_weights", ctypes.c_int, [_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, _p,
                                             ctypes.POINTER(ctypes.c_int)])
+_sig("ed_lowest_levels", ctypes.c_int, [ctypes.c_int, _p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ed_lanczos_opts),
+                                        ctypes.c_uint64, ctypes.POINTER(_p), _p])
+_sig("ed_levels_info", ctypes.c_int, [_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)])
+_sig("ed_levels_get", ctypes.c_int, [_p, _p, _p, _p])
+_sig("ed_levels_capped", ctypes.c_int, [_p, _p])
+_sig("ed_levels_vector", ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int, _p, _p])
+_sig("ed_levels_free", None, [_p])
 if hasattr(_lib, "ed_lanczos_ground_batched"):
     _sig("ed_batched_workspace_bytes", ctypes.c_int, [ctypes.c_int, _p, ctypes.POINTER(ed_lanczos_opts),
                                                       ctypes.POINTER(ctypes.c_size_t)])
@@ -487,70 +495,46 @@ def green_function(H0: "Hamiltonian", e0: float, psi0, Hp: "Hamiltonian", Hm: "H
 
 def lowest_levels(hams: Sequence["Hamiltonian"], K: int, opts=None, seed: int = 1, kmax: int = 200, progress=None):
     """The K lowest levels, counted with multiplicity, over the sectors `hams`
-    (the thermal set behind Eq. 3).  Ground energies of every sector come from
-    one batched run (ed_lanczos_ground_batched).  Then, as long as some sector
-    that still has levels left has its highest computed level at or below the
-    K-th lowest level found so far, the one whose highest level is lowest gets
-    more levels (ed_arnoldi_lowest, then ed_arnoldi_lowest_more on top of the
-    converged ones): only such a sector can hold another of the K.  Returns
-    (levels, vectors, details): levels = [(E, sector index, level index)]
-    ascending (the K lowest, more where a multiplet straddles the K-th),
-    vectors = {sector index: DEVICE tensor [k, D]} for the sectors with a level
-    in the list, details = counts and the sectors capped at kmax.  progress:
-    optional callable taking one line of text every 50 extensions."""
+    (ed_lowest_levels: the search runs in the library).  Returns (levels,
+    vectors, details): levels = [(E, sector index, level index)] ascending (the
+    K lowest, more where a multiplet straddles the K-th), vectors = {sector
+    index: DEVICE tensor [k, D]} holding levels 0..k-1 of each sector that has
+    a level in the list, details = counts, the capped sectors and the
+    threshold.  progress: optional callable given one summary line."""
     import torch
+    o = opts if opts is not None else options()
     n = len(hams)
-    E0, _ = lanczos_ground_batched(hams, opts, seed=seed)
-    energies = {s: [float(E0[s])] for s in range(n)}
-    vecs = {}
-    calls = 0
-
-    def extend(s, k):
-        nonlocal calls
-        H = hams[s]
-        dt = torch.float64 if H.precision == ED_FP64 else torch.float32
-        v0 = torch.empty(H.D, dtype=dt, device="cuda")
-        fill_random(v0, seed + s, 1)
-        ev = torch.empty((k, H.D), dtype=dt, device="cuda")
-        try:
-            if s in vecs:
-                k0 = vecs[s].shape[0]
-                ev[:k0].copy_(vecs[s])
-                E, _ = H.lowest_more(k0, k, energies[s], v0, ev, opts)
-            else:
-                E, _ = H.lowest(k, v0, opts, evecs=ev)
-        except EDError as err:
-            raise EDError(err.status, "sector %d (D=%d), k=%d: %s" % (s, H.D, k, err)) from None
-        energies[s] = [float(e) for e in E]   # discovery order (ascending up to rounding) = row order
-        vecs[s] = ev
-        calls += 1
-
-    def threshold():
-        allE = sorted(e for es in energies.values() for e in es)
-        return allE[K - 1] if len(allE) >= K else float("inf")
-
-    capped = set()
-    while True:
-        T = threshold()
-        cand = [s for s in range(n) if max(energies[s]) <= T]
-        for s in cand:
-            if len(energies[s]) >= min(hams[s].D, kmax) and len(energies[s]) < hams[s].D:
-                capped.add(s)
-        cand = [s for s in cand if len(energies[s]) < min(hams[s].D, kmax)]
-        if not cand:
-            break
-        s = min(cand, key=lambda q: max(energies[q]))
-        k = len(energies[s]) if s in vecs else 0
-        extend(s, min(hams[s].D, kmax, k + max(2, k // 4)))
-        if progress and calls % 50 == 0:
-            progress("lowest_levels: %d extensions, K-th level %.6g" % (calls, T))
-    T = threshold()
-    levels = sorted((e, s, i) for s, es in energies.items() for i, e in enumerate(es) if e <= T)
-    for s in sorted({s for _, s, _ in levels} - set(vecs)):
-        extend(s, 1)                 # one-level sectors: ground energy known, vector not yet
-    levels = sorted((e, s, i) for s, es in energies.items() for i, e in enumerate(es) if e <= T)
-    return levels, {s: vecs[s] for s in {s for _, s, _ in levels}}, {"lowest_calls": calls,
-                                                                    "capped": sorted(capped), "threshold": T}
+    hs = (_p * n)(*[h._h for h in hams])
+    L = _p()
+    _check(_lib.ed_lowest_levels(n, ctypes.cast(hs, _p), int(K), int(kmax), ctypes.byref(o), seed & 0xFFFFFFFFFFFFFFFF,
+                                 ctypes.byref(L), _stream(None)))
+    try:
+        nl, calls, ncap, thr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(_lib.ed_levels_info(L, ctypes.byref(nl), ctypes.byref(calls), ctypes.byref(ncap), ctypes.byref(thr)))
+        E = np.zeros(max(nl.value, 1))
+        sec = np.zeros(max(nl.value, 1), dtype=np.int32)
+        idx = np.zeros(max(nl.value, 1), dtype=np.int32)
+        _check(_lib.ed_levels_get(L, E.ctypes.data_as(_p), sec.ctypes.data_as(_p), idx.ctypes.data_as(_p)))
+        capped = np.zeros(max(ncap.value, 1), dtype=np.int32)
+        if ncap.value:
+            _check(_lib.ed_levels_capped(L, capped.ctypes.data_as(_p)))
+        levels = [(float(E[i]), int(sec[i]), int(idx[i])) for i in range(nl.value)]
+        vecs = {}
+        for s in sorted({q for _, q, _ in levels}):
+            H = hams[s]
+            k = 1 + max(i for _, q, i in levels if q == s)
+            dt = torch.float64 if H.precision == ED_FP64 else torch.float32
+            v = torch.empty((k, H.D), dtype=dt, device="cuda")
+            for i in range(k):
+                _check(_lib.ed_levels_vector(L, s, i, _dev_ptr(v[i]), _stream(None)))
+            vecs[s] = v
+        torch.cuda.synchronize()
+    finally:
+        _lib.ed_levels_free(L)
+    det = {"lowest_calls": calls.value, "capped": [int(c) for c in capped[:ncap.value]], "threshold": thr.value}
+    if progress:
+        progress("lowest_levels: %d levels, %d solver calls, threshold %.6g" % (len(levels), calls.value, thr.value))
+    return levels, vecs, det
 
 
 def green_thermal(params: Dict, ns: int, sectors: Sequence[Tuple[int, int]], spin: int, site: int, beta: float, z,
