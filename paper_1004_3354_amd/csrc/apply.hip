@@ -1061,7 +1061,10 @@ __global__ __launch_bounds__(BS) void k_upt(ApplyArgs<TX, TA> a) {
 // four-fermion terms move both spins to other components and read memory.
 // UPX = false leaves H_up (x) 1 to a band pass.  Element offsets are 32-bit
 // (D < 2^32).
-template <typename TX, typename TA, int R, int BS, bool UPX>
+// FOLD: the cross term is one table over the fk sites of every w_ud entry
+// (diagonal = e_up + e_dn + T[(c_up << fk) | c_dn]); otherwise it is a uniform
+// on-site U, U0 popc(s_up & s_dn & umask), and nothing else.
+template <typename TX, typename TA, int R, int BS, bool UPX, bool FOLD>
 __global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
     using RVt = typename RV<TX, R>::t;
     using V = typename V4<TX>::t;
@@ -1082,10 +1085,8 @@ __global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
     const uint32_t w0 = (uint32_t)a.win[wi].x;
     const int wl = a.win[wi].y;
     for (int k = threadIdx.x; k < a.namp; k += BS) amps[k] = a.amp_tab[k];
-    if (a.umode == 2)
-        for (int k = threadIdx.x; k < 32; k += BS) usl[k] = a.usite[k];
-    if (a.koff)
-        for (int k = threadIdx.x; k < (1 << (2 * a.koff)); k += BS) xtl[k] = a.xtab[k];
+    if constexpr (FOLD)
+        for (int k = threadIdx.x; k < (1 << (2 * a.fk)); k += BS) xtl[k] = a.ftab[k];
     uint32_t ur[R], su[R], cu[R];
     TA eu[R];
     int nu[R], nxl[R];
@@ -1095,8 +1096,13 @@ __global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
         const uint32_t u = (uint32_t)it.x + (ok ? r : 0);
         ur[r] = u;
         eu[r] = ok ? a.up_e[u] : (TA)0;
-        su[r] = ok ? a.up_st[u] : 0u;
-        cu[r] = ok ? a.up_c[u] : 0u;
+        if constexpr (FOLD) {
+            su[r] = 0u;
+            cu[r] = ok ? ((uint32_t)a.up_fc[u] << a.fk) : 0u;
+        } else {
+            su[r] = ok ? (a.up_st[u] & a.umask) : 0u;
+            cu[r] = 0u;
+        }
         const int32_t hb = a.up_off[u];
         const int n = ok && UPX ? a.up_off[u + 1] - hb : 0;
         nu[r] = (n + 3) & ~3;
@@ -1145,14 +1151,15 @@ __global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
     for (int cl = 4 * (int)threadIdx.x; cl < wl; cl += 4 * BS) {
         const bool full = cl + 4 <= wl;
         const uint32_t c = w0 + (uint32_t)cl;
+        // the column data first (the diagonal depends on it)
         TA edn[4];
-        uint32_t sd[4], cd[4];
+        uint32_t cd[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const bool ok = cl + j < wl;
-            edn[j] = ok ? (TA)a.dn_e[c + j] : (TA)0;
-            sd[j] = ok ? a.dn_st[c + j] : 0u;
-            cd[j] = ok ? (uint32_t)a.dn_c[c + j] : 0u;
+            const uint32_t q = c + (uint32_t)min(j, wl - 1 - cl);  // ragged end: repeat the last column
+            edn[j] = (TA)a.dn_e[q];
+            if constexpr (FOLD) cd[j] = a.dn_fc[q];
+            else cd[j] = a.dn_st[q];
         }
         TA acc[R][4];
 #pragma unroll
@@ -1160,9 +1167,12 @@ __global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
             const uint32_t l = (uint32_t)min(cl + j, wl - 1);
             const RVt v = *reinterpret_cast<const RVt *>(xs + l * R);
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                acc[r][j] = (eu[r] + edn[j] + cross_term_l(a, usl, xtl, su[r], sd[j], cu[r], cd[j])) *
-                            (TA)rv_get<TX, R>(v, r);
+            for (int r = 0; r < R; ++r) {
+                TA dg;
+                if constexpr (FOLD) dg = eu[r] + edn[j] + xtl[cu[r] | cd[j]];
+                else dg = eu[r] + edn[j] + a.U0 * (TA)__popc(su[r] & cd[j]);
+                acc[r][j] = dg * (TA)rv_get<TX, R>(v, r);
+            }
         }
         // 1 (x) H_dn: the window's table (padding entries have amplitude 0
         // and a target inside the window)
@@ -1625,6 +1635,10 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.partials = partials;
     a.theta = theta;
     a.items = nullptr;
+    a.fk = h->fk;
+    a.ftab = h->ftab64.as<double>();
+    a.up_fc = h->fcidx[0].as<uint8_t>();
+    a.dn_fc = h->fcidx[1].as<uint8_t>();
     return a;
 }
 
@@ -1676,6 +1690,10 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.partials = partials;
     a.theta = theta;
     a.items = nullptr;
+    a.fk = h->fk;
+    a.ftab = h->ftab32.as<float>();
+    a.up_fc = h->fcidx[0].as<uint8_t>();
+    a.dn_fc = h->fcidx[1].as<uint8_t>();
     return a;
 }
 
@@ -1789,6 +1807,8 @@ static void launch_upb(const ApplyArgs<TX, TA> &a, int64_t band, int rw, hipStre
 
 template <typename TX, typename TA, int R, int BS, bool UPX = true>
 static void launch_gtile(ed_ham_s *h, ApplyArgs<TX, TA> a, int64_t wtarget, hipStream_t s) {
+    if (h->fk < 0 && !(h->koff == 0 && h->umode <= 1))
+        fail(ED_EINVAL, "tile schedule: the cross term is neither a small table nor a uniform on-site U");
     const TilePlan *t = tile_plan(h, R, wtarget);
     a.win = t->win.as<int2>();
     a.nwin = t->nwin;
@@ -1800,9 +1820,15 @@ static void launch_gtile(ed_ham_s *h, ApplyArgs<TX, TA> a, int64_t wtarget, hipS
     a.namp = t->namp;
     a.amp_tab = sizeof(TA) == 8 ? (const TA *)t->amp64.p : (const TA *)t->amp32.p;
     const size_t shm = (((size_t)R * (size_t)t->wmax * sizeof(TX) + 15) & ~(size_t)15) + (size_t)t->namp * sizeof(TA);
-    auto kern = k_gtile<TX, TA, R, BS, UPX>;
-    allow_lds(kern);
-    kern<<<(unsigned)t->nitems, BS, shm, s>>>(a);
+    if (h->fk >= 0) {
+        auto kern = k_gtile<TX, TA, R, BS, UPX, true>;
+        allow_lds(kern);
+        kern<<<(unsigned)t->nitems, BS, shm, s>>>(a);
+    } else {
+        auto kern = k_gtile<TX, TA, R, BS, UPX, false>;
+        allow_lds(kern);
+        kern<<<(unsigned)t->nitems, BS, shm, s>>>(a);
+    }
     ED_LAUNCH_CHECK();
 }
 
@@ -1922,9 +1948,10 @@ static bool variant_fits(const ed_ham_s *h, int v, size_t elem) {
     if (V.kind == 8 && V.BS > 512 && cs_kmax(h) > 16) return false;
     if (V.kind == 12 || V.kind == 13) {
         // grouped tile kernel: every down component whole in a window that fits LDS
-        if (!h->grouped || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->koff > 4 || h->D >= ((int64_t)1 << 32) ||
+        if (!h->grouped || h->sp[0].max_hops > 32 || h->xl_max > 16 || h->D >= ((int64_t)1 << 32) ||
             h->ddn >= (1 << 20))
             return false;
+        if (h->fk < 0 && !(h->koff == 0 && h->umode <= 1)) return false;
         const int64_t wmax = std::max<int64_t>(max_down_component(h), std::min<int64_t>(V.band, h->ddn));
         if ((int64_t)V.R * wmax * (int64_t)elem + 4096 * (int64_t)elem + 16 > kDynBudget) return false;
         if (max_down_component(h) > 2 * V.band) return false;

@@ -199,6 +199,12 @@ struct ed_ham_s {
     ed::DevMem usite64, usite32;  // [32]
     int koff = 0;               // number of sites carrying off-diagonal w_ud entries
     ed::DevMem xtab64, xtab32;  // [4^koff]
+    // the whole cross term sum_ij w_ud[i][j] n_i,up n_j,dn as one table when
+    // every nonzero w_ud entry lies on at most 4 sites: fk sites, per state the
+    // bits on them (fcidx) and the 4^fk values
+    int fk = -1;                // -1: no folded table
+    ed::DevMem fcidx[2];
+    ed::DevMem ftab64, ftab32;
     // four-fermion terms
     int nx = 0;
     std::vector<ed::XTerm> xterms;
@@ -216,7 +222,8 @@ struct ed_ham_s {
     // Grouped basis order.  On a handle built in that order (grouped = true)
     // the states of each spin are ordered by connected component of the
     // one-spin move graph (hops and same-spin two-body moves), components by
-    // their lowest rank, states within a component by rank; every index of its
+    // their lowest rank, states within a component by number of hops
+    // (descending), then rank; every index of its
     // tables and vectors is a position in that order.  gperm[s][p] = rank of
     // position p, gipos[s][r] = position of rank r, comp_off[s] = component
     // boundaries.  A rank-order handle whose move graphs have several
@@ -292,6 +299,10 @@ struct ApplyArgs {
     // grouped tile kernel: per-window slices of the down hop table
     const int32_t *wsl_first, *wsl_off;
     const uint4 *wel4;
+    // folded cross-term table (fk < 0: none)
+    int fk;
+    const TA *ftab;
+    const uint8_t *up_fc, *dn_fc;
 };
 
 // Build all tables of a Hamiltonian handle (tables.hip).

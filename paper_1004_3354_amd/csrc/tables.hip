@@ -543,6 +543,42 @@ static void build_cross(ed_ham_s *h, const ed_params *p) {
             ED_HIP(hipMemset(h->sp[s].cidx.p, 0, (size_t)h->sp[s].dim));
         }
     }
+    // the whole cross term as one table when its sites are few
+    {
+        std::vector<int> fs;
+        for (int i = 0; i < ns; ++i) {
+            bool any = false;
+            for (int j = 0; j < ns; ++j)
+                if (w[i * ns + j] != 0.0 || w[j * ns + i] != 0.0) any = true;
+            if (any) fs.push_back(i);
+        }
+        h->fk = -1;
+        if (fs.size() <= 4) {
+            const int k = (int)fs.size(), nt = 1 << k;
+            std::vector<double> tab((size_t)nt * nt, 0.0);
+            for (int cu = 0; cu < nt; ++cu)
+                for (int cd = 0; cd < nt; ++cd) {
+                    double e = 0.0;
+                    for (int a = 0; a < k; ++a)
+                        for (int c = 0; c < k; ++c)
+                            if (((cu >> a) & 1) && ((cd >> c) & 1)) e += w[fs[a] * ns + fs[c]];
+                    tab[(size_t)cu * nt + cd] = e;
+                }
+            upload(h->ftab64, tab);
+            upload(h->ftab32, std::vector<float>(tab.begin(), tab.end()));
+            DevMem dsites;
+            upload(dsites, fs.empty() ? std::vector<int>{0} : fs);
+            for (int s = 0; s < 2; ++s) {
+                SpinTab &t = h->sp[s];
+                h->fcidx[s].alloc((size_t)t.dim);
+                k_cidx<<<grid_for(t.dim, 256, 1 << 16), 256>>>(t.states.as<uint32_t>(), t.dim, dsites.as<int>(), k,
+                                                              h->fcidx[s].as<uint8_t>());
+                ED_LAUNCH_CHECK();
+            }
+            ED_HIP(hipDeviceSynchronize());
+            h->fk = k;
+        }
+    }
 }
 
 // Four-fermion terms as products of one-spin moves (Section 4):
@@ -727,7 +763,8 @@ static void validate(const ed_params *p, int ns) {
 
 // Connected components of one spin's move graph (the hop table, which also
 // holds the same-spin two-body moves) by union-find; the grouped order lists
-// the components by their lowest rank and each component's states by rank.
+// the components by their lowest rank and each component's states by number
+// of hops (descending), then by rank.
 // Returns the number of components; perm[p] = rank at position p.
 static int component_order(const SpinTab &t, std::vector<int32_t> &perm, std::vector<int32_t> &comp_off) {
     const int64_t dim = t.dim;
@@ -765,6 +802,13 @@ static int component_order(const SpinTab &t, std::vector<int32_t> &perm, std::ve
         }
     perm.assign((size_t)dim, 0);
     for (int64_t r = 0; r < dim; ++r) perm[start[root[r]]++] = (int32_t)r;
+    // within a component: more hops first, then by rank, so that runs of
+    // consecutive positions (the slices of the tile kernels' hop tables) hold
+    // states with similar hop counts and little padding
+    for (size_t c = 0; c + 1 < comp_off.size(); ++c)
+        std::stable_sort(perm.begin() + comp_off[c], perm.begin() + comp_off[c + 1], [&](int32_t a, int32_t b) {
+            return off[a + 1] - off[a] > off[b + 1] - off[b];
+        });
     return (int)comp_off.size() - 1;
 }
 

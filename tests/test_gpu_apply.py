@@ -303,8 +303,8 @@ def _components(off, tgt):
 
 @pytest.mark.parametrize("name,phys,sec_nn", GROUPED[:4], ids=[c[0] for c in GROUPED[:4]])
 def test_grouped_order_and_tables(name, phys, sec_nn):
-    """The grouped order is a permutation that keeps ranks ascending inside
-    each component, every hop of the twin stays inside its component, and the
+    """The grouped order is a permutation that orders each component's states
+    by hop count (descending), then rank; every hop of the twin stays inside its component, and the
     twin's hop table translated back to ranks is the oracle's (bit for bit,
     per row as a set of (target, sign, amplitude))."""
     ed = gpu_ed()
@@ -331,11 +331,13 @@ def test_grouped_order_and_tables(name, phys, sec_nn):
                         changed = True
             if not changed:
                 break
-        # contiguous components, ranks ascending inside each
+        # contiguous components; inside each, more hops first, then ascending rank
         starts = np.nonzero(np.r_[True, comp[1:] != comp[:-1]])[0]
         assert len(np.unique(comp)) == len(starts)
+        nh = np.diff(o_off)[perm]
         for a, z in zip(starts, np.r_[starts[1:], D]):
-            assert np.all(np.diff(perm[a:z]) > 0)
+            key = list(zip((-nh[a:z]).tolist(), perm[a:z].tolist()))
+            assert key == sorted(key)
         for i in range(D):
             r = perm[i]
             mine = sorted(zip(perm[tgt[off[i]:off[i + 1]]].tolist(), sgn[off[i]:off[i + 1]].tolist(),
