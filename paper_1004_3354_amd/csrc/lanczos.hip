@@ -329,40 +329,91 @@ __global__ __launch_bounds__(kRedBS) void k_lincomb_v4(const TX *const *vecs, co
 
 // Implicit restart, in place: out_o[n] = sum_i C[i * nout + o] in_i[n] for
 // o < nout, where out_o is the storage of in_o (each element's inputs are read
-// by the thread that writes its outputs, before it writes them).  Norm partials
-// of the last output (the new residual).
-template <typename TX>
-__global__ __launch_bounds__(kRedBS) void k_restart_combine(const TX *const *vin, const double *C, int nin, int nout,
-                                                            int64_t n, double *norm_part) {
-    __shared__ double c[kIRMaxIn * kIRMaxOut];
+// by the thread that writes its outputs, before it writes them).  Four
+// consecutive elements per thread, two inputs' loads in flight, FP64
+// accumulation; NO >= nout is the compile-time output count (coefficients
+// padded with zeros, so the inner loop has no branches).  Norm partials of the
+// last output (the new residual).
+template <typename TX, int NO>
+__global__ __launch_bounds__(kRedBS) void k_restart_combine_v4(const TX *const *vin, const double *C, int nin,
+                                                               int nout, int64_t n, double *norm_part) {
+    __shared__ double c[kIRMaxIn * NO];
     __shared__ const TX *pin[kIRMaxIn];
     __shared__ double red[kRedBS / 64];
-    for (int i = threadIdx.x; i < nin * nout; i += kRedBS) c[i] = C[i];
+    for (int i = threadIdx.x; i < nin * NO; i += kRedBS) {
+        const int r = i / NO, o = i - r * NO;
+        c[i] = o < nout ? C[r * nout + o] : 0.0;
+    }
     for (int i = threadIdx.x; i < nin; i += kRedBS) pin[i] = vin[i];
     __syncthreads();
     int64_t a, b;
     block_range(n, gridDim.x, blockIdx.x, a, b);
     double nrm = 0.0;
-    for (int64_t k = a + threadIdx.x; k < b; k += kRedBS) {
-        double acc[kIRMaxOut];
+    int64_t k = a + 4 * (int64_t)threadIdx.x;
+    for (; k + 4 <= b; k += 4 * kRedBS) {
+        double acc[NO][4];
 #pragma unroll
-        for (int o = 0; o < kIRMaxOut; ++o) acc[o] = 0.0;
-        for (int i = 0; i < nin; ++i) {
-            const double v = (double)pin[i][k];
+        for (int o = 0; o < NO; ++o)
 #pragma unroll
-            for (int o = 0; o < kIRMaxOut; ++o)
-                if (o < nout) acc[o] += c[i * nout + o] * v;
+            for (int e = 0; e < 4; ++e) acc[o][e] = 0.0;
+        int i = 0;
+        for (; i + 2 <= nin; i += 2) {
+            const Q4<TX> v0 = load4(pin[i] + k), v1 = load4(pin[i + 1] + k);
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                const double c0 = c[i * NO + o], c1 = c[(i + 1) * NO + o];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[o][e] += c0 * (double)v0.v[e] + c1 * (double)v1.v[e];
+            }
+        }
+        if (i < nin) {
+            const Q4<TX> v0 = load4(pin[i] + k);
+#pragma unroll
+            for (int o = 0; o < NO; ++o)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[o][e] += c[i * NO + o] * (double)v0.v[e];
         }
 #pragma unroll
-        for (int o = 0; o < kIRMaxOut; ++o)
+        for (int o = 0; o < NO; ++o)
+            if (o < nout) {
+                Q4<TX> q;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) q.v[e] = (TX)acc[o][e];
+                store4(const_cast<TX *>(pin[o]) + k, q);
+                if (o == nout - 1)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) nrm += (double)q.v[e] * (double)q.v[e];
+            }
+    }
+    for (int64_t e = k; e < b && e < k + 4; ++e) {  // ragged end of the block
+        double acc[NO];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+        for (int i = 0; i < nin; ++i) {
+            const double v = (double)pin[i][e];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) acc[o] += c[i * NO + o] * v;
+        }
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
             if (o < nout) {
                 const TX st = (TX)acc[o];
-                const_cast<TX *>(pin[o])[k] = st;
+                const_cast<TX *>(pin[o])[e] = st;
                 if (o == nout - 1) nrm += (double)st * (double)st;
             }
     }
     const double sm = block_sum_any<kRedBS>(nrm, red);
     if (threadIdx.x == 0) norm_part[blockIdx.x] = sm;
+}
+
+template <typename TX>
+static void launch_restart_combine(const TX *const *vin, const double *C, int nin, int nout, int64_t n,
+                                   double *norm_part, int nblk, hipStream_t s) {
+    if (nout <= 2) k_restart_combine_v4<TX, 2><<<nblk, kRedBS, 0, s>>>(vin, C, nin, nout, n, norm_part);
+    else if (nout <= 3) k_restart_combine_v4<TX, 3><<<nblk, kRedBS, 0, s>>>(vin, C, nin, nout, n, norm_part);
+    else if (nout <= 5) k_restart_combine_v4<TX, 5><<<nblk, kRedBS, 0, s>>>(vin, C, nin, nout, n, norm_part);
+    else if (nout <= 9) k_restart_combine_v4<TX, 9><<<nblk, kRedBS, 0, s>>>(vin, C, nin, nout, n, norm_part);
+    else k_restart_combine_v4<TX, kIRMaxOut><<<nblk, kRedBS, 0, s>>>(vin, C, nin, nout, n, norm_part);
 }
 
 __global__ void k_scale(void *y, int64_t n, double f, int is_f32) {
@@ -375,6 +426,73 @@ __global__ void k_scale(void *y, int64_t n, double f, int is_f32) {
             p[k] = p[k] * f;
         }
     }
+}
+
+// Fixed-order sum of p[0..n), n <= 8 * 256, by one workgroup of 256: thread
+// t adds p[t], p[t + 256], ... in that order (all its loads issued at once),
+// then a shared-memory tree.  The result is valid in thread 0.
+__device__ __forceinline__ double wg_sum_fixed(const double *p, int n, double *sh) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int i = (int)threadIdx.x + 256 * q;
+        v[q] = i < n ? p[i] : 0.0;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += v[q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// One workgroup per vector v (grid = nvec): raw[v] = sum of the v-th row of
+// partials, gamma[v] = sig2[v] raw[v]; the workgroup of v = jidx adds
+// gamma[jidx] to *alpha.
+__global__ __launch_bounds__(256) void k_finalize_dots_par(const double *partials, int nblk, const double *sig2,
+                                                          double *raw, double *gamma, double *alpha, int jidx) {
+    __shared__ double sh[256];
+    const int v = blockIdx.x;
+    const double s = wg_sum_fixed(partials + (int64_t)v * nblk, nblk, sh);
+    if (threadIdx.x == 0) {
+        if (raw) raw[v] = s;
+        const double g = (sig2 ? sig2[v] : 1.0) * s;
+        if (gamma) gamma[v] = g;
+        if (alpha && gamma && v == jidx) *alpha += g;
+    }
+}
+
+// Row sums of the two-sided multi-dot (grid = 2 nvec): out[v] = sum of row v.
+__global__ __launch_bounds__(256) void k_rowsums(const double *partials, int nblk, double *out) {
+    __shared__ double sh[256];
+    const double s = wg_sum_fixed(partials + (int64_t)blockIdx.x * nblk, nblk, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// The coefficients of both projections from the row sums (reorth = 3): as
+// k_finalize_gram, with a[0..nvec) = <S_i, Y> and g = a[nvec..2 nvec) =
+// <S_i, S_jr> already summed.  One workgroup.
+__global__ __launch_bounds__(256) void k_gram_coef(const double *sums, int nvec, const double *sig2, double *gram,
+                                                  int ld, double *gamma, double *alpha) {
+    __shared__ double g1[kMaxVec];
+    const int jr = nvec - 1;
+    for (int i = threadIdx.x; i < nvec; i += 256) {
+        g1[i] = sig2[i] * sums[i];
+        gram[(int64_t)jr * ld + i] = sums[nvec + i];
+        gram[(int64_t)i * ld + jr] = sums[nvec + i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nvec; i += 256) {
+        double t = 0.0;
+        for (int k = 0; k < nvec; ++k) t += gram[(int64_t)i * ld + k] * g1[k];
+        gamma[i] = g1[i] + sig2[i] * (sums[i] - t);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && alpha) *alpha += gamma[jr];
 }
 
 // Fixed-order sum of partials[v*nblk + 0..nblk) for each v; gamma[v] =
@@ -445,16 +563,9 @@ __global__ __launch_bounds__(256) void k_finalize_gram(const double *partials, i
 // n2 = ||w''||^2 -> beta[j] = sqrt(n2), sig2[j+1] = 1/n2 (0 on exact breakdown).
 __global__ void k_finalize_norm(const double *partials, int nblk, double *sig2, double *beta, int jidx, int j) {
     __shared__ double sh[256];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += 256) s += partials[i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
+    const double n2s = wg_sum_fixed(partials, nblk, sh);
     if (threadIdx.x == 0) {
-        const double n2 = sh[0];
+        const double n2 = n2s;
         beta[j] = sqrt(n2);
         sig2[jidx + 1] = n2 > 0.0 ? 1.0 / n2 : 0.0;
     }
@@ -473,14 +584,23 @@ __device__ int sturm_count(const double *al, const double *be, int m, double x, 
     return c;
 }
 
-// Lowest eigenpair of the m x m symmetric tridiagonal (alpha, beta) matrix.
-// out[0] = theta, out[1] = |beta_last s_{m-1}|, out[2] = beta_last,
-// out[3 .. 3+m) = normalised eigenvector.  One workgroup of 256 threads.
+// Lowest eigenpair of the m x m symmetric tridiagonal (alpha, beta) matrix,
+// m <= kTriMax.  out[0] = theta, out[1] = |beta_last s_{m-1}|, out[2] =
+// beta_last, out[3 .. 3+m) = normalised eigenvector.  One workgroup of 256
+// threads: 256-point multisection on the Sturm count (the first point whose
+// count reaches 1 found by an LDS minimum), then thread 0 does inverse
+// iteration on T - theta I with one LU factorisation (partial pivoting) and
+// three solves; the running values of each recurrence stay in registers and
+// the factors in LDS.  `work` is unused (kept for the callers' layout).
+static constexpr int kTriMax = 1024;
 __device__ void k_tridiag_lowest_body(const double *alpha, const double *beta, int m, double *out,
                                       double *work) {
-    __shared__ double al[1024], be[1024];
-    __shared__ int cnt[256];
-    __shared__ double lo, hi;
+    (void)work;
+    __shared__ double al[kTriMax], be[kTriMax];
+    __shared__ double fd[kTriMax], fl[kTriMax], fu[kTriMax], fu2[kTriMax], z[kTriMax];
+    __shared__ unsigned char piv[kTriMax];
+    __shared__ int first;
+    __shared__ double lo, hi, pivs;
     const int t = threadIdx.x;
     for (int i = t; i < m; i += 256) {
         al[i] = alpha[i];
@@ -498,24 +618,22 @@ __device__ void k_tridiag_lowest_body(const double *alpha, const double *beta, i
         const double w = 1e-12 * fmax(fmax(fabs(l), fabs(h)), 1.0);
         lo = l - w;
         hi = h + w;
-        work[0] = fmax(1e-290, 1e-300 * bmax * bmax);
+        pivs = fmax(1e-290, 1e-300 * bmax * bmax);
     }
     __syncthreads();
-    const double pivmin = work[0];
+    const double pivmin = pivs;
     for (int it = 0; it < 60; ++it) {
         const double L = lo, H = hi;
         const double x = L + (H - L) * (double)(t + 1) / 257.0;
-        cnt[t] = sturm_count(al, be, m, x, pivmin);
+        const int c = sturm_count(al, be, m, x, pivmin);
+        if (t == 0) first = 256;
+        __syncthreads();
+        if (c >= 1) atomicMin(&first, t);
         __syncthreads();
         if (t == 0) {
-            int f = -1;
-            for (int k = 0; k < 256; ++k)
-                if (cnt[k] >= 1) {
-                    f = k;
-                    break;
-                }
+            const int f = first;
             double nl, nh;
-            if (f < 0) {
+            if (f == 256) {
                 nl = L + (H - L) * 256.0 / 257.0;
                 nh = H;
             } else {
@@ -530,55 +648,64 @@ __device__ void k_tridiag_lowest_body(const double *alpha, const double *beta, i
     }
     if (t != 0) return;
     const double theta = 0.5 * (lo + hi);
-    // inverse iteration with Gaussian elimination and partial pivoting
-    double *d = work + 8, *dl = d + m, *du = dl + m, *du2 = du + m, *z = du2 + m;
-    int *piv = (int *)(z + m);
-    for (int i = 0; i < m; ++i) z[i] = 1.0;
-    for (int rep = 0; rep < 3; ++rep) {
-        for (int i = 0; i < m; ++i) {
-            d[i] = al[i] - theta;
-            dl[i] = (i < m - 1) ? be[i] : 0.0;
-            du[i] = (i < m - 1) ? be[i] : 0.0;
-            du2[i] = 0.0;
-            piv[i] = 0;
-        }
-        const double tiny = 1e-300 + 2.220446049250313e-16 * fmax(fabs(theta), 1.0) * 1e-3;
+    const double tiny = 1e-300 + 2.220446049250313e-16 * fmax(fabs(theta), 1.0) * 1e-3;
+    // T - theta I = P L U: row i of U is (fd[i], fu[i], fu2[i]); fl[i] the multiplier
+    {
+        double cd = al[0] - theta, cdu = m > 1 ? be[0] : 0.0;
         for (int i = 0; i < m - 1; ++i) {
-            if (fabs(d[i]) >= fabs(dl[i])) {
-                if (d[i] == 0.0) d[i] = tiny;
-                const double f = dl[i] / d[i];
-                dl[i] = f;
-                d[i + 1] -= f * du[i];
+            const double sub = be[i];
+            double nd = al[i + 1] - theta;
+            double ndu = (i + 1 < m - 1) ? be[i + 1] : 0.0;
+            double f;
+            if (fabs(cd) >= fabs(sub)) {
+                if (cd == 0.0) cd = tiny;
+                f = sub / cd;
+                fd[i] = cd;
+                fu[i] = cdu;
+                fu2[i] = 0.0;
+                nd -= f * cdu;
                 piv[i] = 0;
-            } else {
-                const double f = d[i] / dl[i];
-                d[i] = dl[i];
-                dl[i] = f;
-                const double tmp = du[i];
-                du[i] = d[i + 1];
-                d[i + 1] = tmp - f * d[i + 1];
-                if (i < m - 2) {
-                    du2[i] = du[i + 1];
-                    du[i + 1] = -f * du[i + 1];
-                }
+            } else {  // rows i and i + 1 swapped
+                f = cd / sub;
+                fd[i] = sub;
+                fu[i] = nd;
+                fu2[i] = (i < m - 2) ? ndu : 0.0;
+                nd = cdu - f * nd;
+                if (i < m - 2) ndu = -f * ndu;
                 piv[i] = 1;
             }
+            fl[i] = f;
+            cd = nd;
+            cdu = ndu;
         }
-        if (d[m - 1] == 0.0) d[m - 1] = tiny;
-        // forward: L
+        if (cd == 0.0) cd = tiny;
+        fd[m - 1] = cd;
+    }
+    for (int i = 0; i < m; ++i) z[i] = 1.0;
+    for (int rep = 0; rep < 3; ++rep) {
+        // z <- L^-1 P z
+        double zc = z[0];
         for (int i = 0; i < m - 1; ++i) {
-            if (piv[i] == 0) {
-                z[i + 1] -= dl[i] * z[i];
+            double zn = z[i + 1];
+            if (!piv[i]) {
+                zn -= fl[i] * zc;
+                z[i] = zc;
             } else {
-                const double tmp = z[i];
-                z[i] = z[i + 1];
-                z[i + 1] = tmp - dl[i] * z[i];
+                z[i] = zn;
+                zn = zc - fl[i] * zn;
             }
+            zc = zn;
         }
-        // backward: U (three diagonals)
-        z[m - 1] /= d[m - 1];
-        if (m > 1) z[m - 2] = (z[m - 2] - du[m - 2] * z[m - 1]) / d[m - 2];
-        for (int i = m - 3; i >= 0; --i) z[i] = (z[i] - du[i] * z[i + 1] - du2[i] * z[i + 2]) / d[i];
+        z[m - 1] = zc;
+        // z <- U^-1 z
+        double z1 = z[m - 1] / fd[m - 1], z2 = 0.0;
+        z[m - 1] = z1;
+        for (int i = m - 2; i >= 0; --i) {
+            const double v = (z[i] - fu[i] * z1 - fu2[i] * z2) / fd[i];
+            z[i] = v;
+            z2 = z1;
+            z1 = v;
+        }
         double mx = 0.0;
         for (int i = 0; i < m; ++i) mx = fmax(mx, fabs(z[i]));
         if (!(mx > 0.0) || !isfinite(mx)) {
@@ -587,19 +714,19 @@ __device__ void k_tridiag_lowest_body(const double *alpha, const double *beta, i
         }
         double nn = 0.0;
         for (int i = 0; i < m; ++i) {
-            z[i] /= mx;
-            nn += z[i] * z[i];
+            const double v = z[i] / mx;
+            z[i] = v;
+            nn += v * v;
         }
         nn = sqrt(nn);
         for (int i = 0; i < m; ++i) z[i] /= nn;
     }
-    if (z[0] < 0.0)
-        for (int i = 0; i < m; ++i) z[i] = -z[i];
+    const double sg = z[0] < 0.0 ? -1.0 : 1.0;
     const double bl = beta[m - 1];
     out[0] = theta;
     out[1] = fabs(bl * z[m - 1]);
     out[2] = bl;
-    for (int i = 0; i < m; ++i) out[3 + i] = z[i];
+    for (int i = 0; i < m; ++i) out[3 + i] = sg * z[i];
 }
 
 __global__ __launch_bounds__(256) void k_tridiag_lowest(const double *alpha, const double *beta, int m,
@@ -778,6 +905,52 @@ static void ir_shift(std::vector<double> &T, std::vector<double> &Q, int m, cons
     }
 }
 
+// Coefficients of the exact-shift implicit restart of a full cycle of m
+// stored steps keeping k vectors.  al[0..m), be[0..m) (be[m-1] is the norm of
+// the residual) and sg[0..m] (1 / ||S_i||^2 of the stored vectors S_0..S_m).
+// C ((m+1) x (k+1), row-major): the kept vectors u_o = sum_l C[l][o] S_l
+// (o < k, orthonormal) and the new residual f = sum_l C[l][k] S_l; a2[0..k),
+// b2[0..k-1) the new leading tridiagonal block; ev the m Ritz values, ascending.
+// false when the restart does not apply (non-finite data, or the kept block no
+// longer holds the lowest Ritz value); the caller then restarts explicitly.
+static bool ir_plan(const std::vector<double> &al, const std::vector<double> &be, const std::vector<double> &sg,
+                    int m, int k, std::vector<double> &C, std::vector<double> &a2, std::vector<double> &b2,
+                    std::vector<double> &ev) {
+    for (int i = 0; i < m; ++i)
+        if (!std::isfinite(al[i]) || !std::isfinite(be[i]) || !(sg[i] > 0.0)) return false;
+    if (!(sg[m] > 0.0)) return false;
+    ev.assign((size_t)m, 0.0);
+    std::vector<double> shifts;
+    for (int i = 0; i < m; ++i) ev[i] = tridiag_eig(al, be, m, i);
+    for (int i = k; i < m; ++i) shifts.push_back(ev[i]);
+    std::vector<double> T((size_t)m * m, 0.0), Q((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) {
+        T[(size_t)i * m + i] = al[i];
+        Q[(size_t)i * m + i] = 1.0;
+        if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = be[i];
+    }
+    ir_shift(T, Q, m, shifts);
+    a2.assign((size_t)k, 0.0);
+    b2.assign((size_t)std::max(k, 1), 0.0);
+    for (int i = 0; i < k; ++i) {
+        a2[i] = T[(size_t)i * m + i];
+        if (i + 1 < k) b2[i] = 0.5 * (T[(size_t)(i + 1) * m + i] + T[(size_t)i * m + i + 1]);
+    }
+    const double t0 = tridiag_eig(a2, b2, k, 0);
+    if (!(std::fabs(t0 - ev[0]) <= 1e-8 * std::max(1.0, std::fabs(ev[0])))) return false;
+    // inputs S_0..S_m, outputs u_0..u_{k-1} and the new residual f
+    const int nin = m + 1, nout = k + 1;
+    const double tk = T[(size_t)k * m + (k - 1)];
+    C.assign((size_t)nin * nout, 0.0);
+    for (int l = 0; l < m; ++l) {
+        const double sl = std::sqrt(sg[l]);
+        for (int o = 0; o < k; ++o) C[(size_t)l * nout + o] = Q[(size_t)l * m + o] * sl;
+        C[(size_t)l * nout + k] = Q[(size_t)l * m + k] * sl * tk;
+    }
+    C[(size_t)m * nout + k] = be[m - 1] * std::sqrt(sg[m]) * Q[(size_t)(m - 1) * m + (k - 1)];
+    return true;
+}
+
 static constexpr int kAutoBasisMax = 120;  // largest planned basis (max_basis = 0)
 
 static void fill_defaults(ed_lanczos_opts &o) {
@@ -830,7 +1003,7 @@ static size_t layout(Work &w, char *base, int64_t D, size_t elem, int m, int kma
     w.vp = (const void **)c.take((size_t)nv * sizeof(void *));
     w.sig2 = (double *)c.take((size_t)nv * sizeof(double));
     w.gamma = (double *)c.take((size_t)nv * sizeof(double));
-    w.raw = (double *)c.take((size_t)nv * sizeof(double));
+    w.raw = (double *)c.take((size_t)2 * nv * sizeof(double));
     w.coef = (double *)c.take((size_t)nv * sizeof(double));
     w.alpha = (double *)c.take((size_t)(m + 2) * sizeof(double));
     w.beta = (double *)c.take((size_t)(m + 2) * sizeof(double));
@@ -868,7 +1041,8 @@ struct Solver {
     void dots(int vbeg, int nvec, const void *y, double *alpha, int jrel) {
         if (h->prec == ED_FP64) multidot<double>(vbeg, nvec, y);
         else multidot<float>(vbeg, nvec, y);
-        k_finalize_dots<<<1, 256, 0, s>>>(w.partials, nvec, w.nblk, w.sig2 + vbeg, w.raw, w.gamma + vbeg, alpha, jrel);
+        k_finalize_dots_par<<<nvec, 256, 0, s>>>(w.partials, w.nblk, w.sig2 + vbeg, w.raw, w.gamma + vbeg, alpha,
+                                                 jrel);
         ED_LAUNCH_CHECK();
     }
     // both projections of one step from a single read of the basis (reorth = 3)
@@ -882,7 +1056,9 @@ struct Solver {
                                                                    (const float *)y, (const float *)z, h->D,
                                                                    w.partials);
         ED_LAUNCH_CHECK();
-        k_finalize_gram<<<1, 256, 0, s>>>(w.partials, nvec, w.nblk, w.sig2, w.gram, w.m + 1, w.gamma, alpha);
+        k_rowsums<<<2 * nvec, 256, 0, s>>>(w.partials, w.nblk, w.raw);
+        ED_LAUNCH_CHECK();
+        k_gram_coef<<<1, 256, 0, s>>>(w.raw, nvec, w.sig2, w.gram, w.m + 1, w.gamma, alpha);
         ED_LAUNCH_CHECK();
     }
     void update(int vbeg, int nvec, void *y, double *normp, const double *post = nullptr) {
@@ -919,7 +1095,7 @@ struct Solver {
     double norm2_sync(int idx, const void *y) {
         if (h->prec == ED_FP64) multidot<double>(idx, 1, y);
         else multidot<float>(idx, 1, y);
-        k_finalize_dots<<<1, 256, 0, s>>>(w.partials, 1, w.nblk, nullptr, w.raw, nullptr, nullptr, 0);
+        k_finalize_dots_par<<<1, 256, 0, s>>>(w.partials, w.nblk, nullptr, w.raw, nullptr, nullptr, 0);
         ED_LAUNCH_CHECK();
         double r = 0.0;
         ED_HIP(hipMemcpyAsync(&r, w.raw, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -961,45 +1137,18 @@ struct Solver {
         // Krylov entries of the pointer and sigma tables follow the nlock locked ones
         ED_HIP(hipMemcpyAsync(sg.data(), w.sig2 + nlock, (size_t)(m + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         ED_HIP(hipStreamSynchronize(s));
-        for (int i = 0; i < m; ++i)
-            if (!std::isfinite(al[i]) || !std::isfinite(be[i]) || !(sg[i] > 0.0)) return false;
-        if (!(sg[m] > 0.0)) return false;
-        std::vector<double> ev((size_t)m), shifts;
-        for (int i = 0; i < m; ++i) ev[i] = tridiag_eig(al, be, m, i);
-        for (int i = k; i < m; ++i) shifts.push_back(ev[i]);
-        std::vector<double> T((size_t)m * m, 0.0), Q((size_t)m * m, 0.0);
-        for (int i = 0; i < m; ++i) {
-            T[(size_t)i * m + i] = al[i];
-            Q[(size_t)i * m + i] = 1.0;
-            if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = be[i];
-        }
-        ir_shift(T, Q, m, shifts);
-        std::vector<double> a2((size_t)k), b2((size_t)std::max(k, 1), 0.0);
-        for (int i = 0; i < k; ++i) {
-            a2[i] = T[(size_t)i * m + i];
-            if (i + 1 < k) b2[i] = 0.5 * (T[(size_t)(i + 1) * m + i] + T[(size_t)i * m + i + 1]);
-        }
-        const double t0 = tridiag_eig(a2, b2, k, 0);
-        if (!(std::fabs(t0 - ev[0]) <= 1e-8 * std::max(1.0, std::fabs(ev[0])))) return false;
-        // inputs S_0..S_m, outputs u_0..u_{k-1} and the new residual f
+        std::vector<double> C, a2, b2, ev;
+        if (!ir_plan(al, be, sg, m, k, C, a2, b2, ev)) return false;
         const int nin = m + 1, nout = k + 1;
-        const double tk = T[(size_t)k * m + (k - 1)];
-        std::vector<double> C((size_t)nin * nout, 0.0);
-        for (int l = 0; l < m; ++l) {
-            const double sl = std::sqrt(sg[l]);
-            for (int o = 0; o < k; ++o) C[(size_t)l * nout + o] = Q[(size_t)l * m + o] * sl;
-            C[(size_t)l * nout + k] = Q[(size_t)l * m + k] * sl * tk;
-        }
-        C[(size_t)m * nout + k] = be[m - 1] * std::sqrt(sg[m]) * Q[(size_t)(m - 1) * m + (k - 1)];
         ED_HIP(hipMemcpyAsync(w.rcoef, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, s));
         if (h->prec == ED_FP64)
-            k_restart_combine<double><<<w.nblk, kRedBS, 0, s>>>((const double *const *)w.vp + nlock, w.rcoef, nin, nout,
-                                                               h->D, w.partials);
+            launch_restart_combine<double>((const double *const *)w.vp + nlock, w.rcoef, nin, nout, h->D, w.partials,
+                                           w.nblk, s);
         else
-            k_restart_combine<float><<<w.nblk, kRedBS, 0, s>>>((const float *const *)w.vp + nlock, w.rcoef, nin, nout,
-                                                              h->D, w.partials);
+            launch_restart_combine<float>((const float *const *)w.vp + nlock, w.rcoef, nin, nout, h->D, w.partials,
+                                          w.nblk, s);
         ED_LAUNCH_CHECK();
-        k_finalize_dots<<<1, 256, 0, s>>>(w.partials, 1, w.nblk, nullptr, w.raw, nullptr, nullptr, 0);
+        k_finalize_dots_par<<<1, 256, 0, s>>>(w.partials, w.nblk, nullptr, w.raw, nullptr, nullptr, 0);
         ED_LAUNCH_CHECK();
         double n2 = 0.0;
         ED_HIP(hipMemcpyAsync(&n2, w.raw, sizeof(double), hipMemcpyDeviceToHost, s));
