@@ -54,6 +54,64 @@ def traffic_from_profile(workload, schedule):
     return e.get("bytes_per_launch")
 
 
+# ---- rocprofv3 summaries (the figures committed under profiles/) -----------
+APPLY_KERNELS = ("k_apply", "k_cs<", "k_csb<", "k_rt<", "k_upb<", "k_upt<", "k_gtile<")
+
+
+def summarize_stats(path):
+    """Per-kernel dispatch count and average duration from a rocprofv3
+    --kernel-trace --stats run (kernel_stats.csv), largest total first."""
+    import csv
+    out = []
+    for r in csv.DictReader(open(path)):
+        name = r.get("Name") or r.get("KernelName") or r.get("Kernel_Name")
+        out.append((name, int(r.get("Calls", 0)), float(r.get("AverageNs", r.get("Average_Ns", 0.0)))))
+    out.sort(key=lambda t: -t[1] * t[2])
+    return out
+
+
+def _per_dispatch(path, counter):
+    import csv
+    from collections import defaultdict
+    vals = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        name = r.get("Kernel_Name") or r.get("Kernel-Name") or r.get("KernelName")
+        cn = r.get("Counter_Name") or r.get("Counter-Name")
+        if cn != counter:
+            continue
+        did = int(r.get("Dispatch_Id") or r.get("Dispatch-Id") or 0)
+        vals[name].append((did, float(r.get("Counter_Value") or r.get("Counter-Value"))))
+    return vals
+
+
+def summarize_traffic(fetch_csv, write_csv, info_json, workload):
+    """HBM bytes per apply launch from a FETCH_SIZE run and a WRITE_SIZE run of
+    --pmc-pass (KiB per dispatch), each scaled by the factor that makes the same
+    counter read the known 4 D bytes of the plain copy kernel in the same run."""
+    info = json.loads([l for l in open(info_json) if l.startswith("{")][-1])
+    steps, cb = info["steps"], info["copy_bytes_each_way"]
+    res = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        v = _per_dispatch(path, counter)
+        copy = [x for n, l in v.items() if "copy" in n.lower() or "elementwise" in n.lower() for x in l]
+        copy = sorted(copy)[-steps:]
+        apply_names = [n for n in v if any(k in n for k in APPLY_KERNELS)]
+        per_launch = 0.0
+        for n in apply_names:  # the last `steps` dispatches of each apply kernel are the timed ones
+            l = sorted(v[n])[-steps:]
+            per_launch += sum(c for _, c in l) / len(l)
+        copy_kib = sum(c for _, c in copy) / max(len(copy), 1)
+        factor = (cb / 1024.0) / copy_kib if copy_kib > 0 else float("nan")
+        res[counter] = {"apply_kib_per_launch": per_launch, "copy_kib": copy_kib, "factor": factor,
+                        "bytes": per_launch * 1024.0 * factor, "kernels": apply_names}
+    total = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
+    return {workload: {"source_hash": kernel_source_hash(), "bytes_per_launch": total,
+                       "fetch_bytes": res["FETCH_SIZE"]["bytes"], "write_bytes": res["WRITE_SIZE"]["bytes"],
+                       "fetch_factor": res["FETCH_SIZE"]["factor"], "write_factor": res["WRITE_SIZE"]["factor"],
+                       "algorithmic_bytes": 8 * info["D"], "schedule": info["schedule"],
+                       "kernels": res["FETCH_SIZE"]["kernels"]}}
+
+
 def schedule_kernels(name):
     """Kernels one apply launches under a schedule (by schedule-name prefix)."""
     for pre, k in (("rtg_", "k_rt (group-aligned tiles)"), ("rtp_", "k_rt (packed group tiles)"),
@@ -156,6 +214,16 @@ def cpu_baseline(cfg=2, max_steps=400, tol=1e-7):
                            "method": "three-term Lanczos on the CSR product (no reorthogonalisation)"}}
 
 
+def step_roofline(info, seconds):
+    """The Lanczos run against the HBM roofline: the algorithmic bytes its
+    kernels moved (ed_info.traffic: x read and y written per H.v, the projected
+    vectors and Y per Gram-Schmidt pass, restarts, Ritz vector and refinement)
+    over the whole solve's wall time, as a fraction of 8 TB/s."""
+    gb = info["traffic"] / 1e9
+    return {"bytes_GB": round(gb, 2), "ms_per_step": round(1e3 * seconds / max(info["iters"], 1), 3),
+            "GBps": round(gb / seconds, 1), "frac": round(gb / seconds / (HBM_PEAK_GBS), 4)}
+
+
 def time_to_e0(cfg, precs, max_basis, tol, seed_idx, reorth=3, keep=0):
     """Same start vector (SplitMix64 normal stream, FP32 = RNE cast of the FP64
     values, filled on the device) and same residual target for each precision.
@@ -182,7 +250,7 @@ def time_to_e0(cfg, precs, max_basis, tol, seed_idx, reorth=3, keep=0):
         key = "fp64" if prec == ed.ED_FP64 else "fp32_mixed"
         out[key] = {"seconds": round(dt_s, 4), "E0": E, "iters": info["iters"], "restarts": info["restarts"],
                     "converged": info["converged"], "residual": info["residual"], "setup_s": round(tset, 3),
-                    "max_basis": m, "keep": kp}
+                    "max_basis": m, "keep": kp, "step_roofline": step_roofline(info, dt_s)}
         log("time-to-E0 %s (reorth %d): %.3f s E0=%.12f iters=%d restarts=%d" % (key, reorth, dt_s, E, info["iters"],
                                                                                   info["restarts"]))
         del ws, y, H, b, v0
@@ -318,8 +386,11 @@ def wl_config(i):
 
 
 def batched_bench():
-    """All 169 sectors of the N_s = 12 three-orbital impurity: one batched FP32-mixed
-    Lanczos (graph-replayed steps) vs the same sectors solved one after another."""
+    """All 169 sectors of the N_s = 12 three-orbital impurity: the batched
+    FP32-mixed Lanczos (graph-replayed steps, per-sector restarts), in the
+    tuned setting (20 stored vectors keeping 8, both projections per basis read)
+    and in the plain one (60 vectors, CGS2, explicit restarts), vs the same
+    sectors solved one after another by the single-sector solver."""
     import numpy as np
     import torch
     from paper_1004_3354_amd import ed, models, workloads as wl
@@ -329,14 +400,44 @@ def batched_bench():
     hs = [ed.Hamiltonian(p, ed.Basis(phys["Ns"], a, b), ed.ED_FP32) for (a, b) in sectors]
     torch.cuda.synchronize()
     tset = time.perf_counter() - t0
-    opts = ed.options(tol=1e-7, max_basis=60)
     seed = wl.start_vector_seed(3)
-    ed.lanczos_ground_batched(hs, opts, seed=seed)          # graph capture + tile tuning
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    E, info = ed.lanczos_ground_batched(hs, opts, seed=seed)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
+    sum_d = int(sum(h.D for h in hs))
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_e0.json")
+    ref = None
+    if os.path.exists(gold):
+        g = json.load(open(gold))["entries"].get("cfg3")
+        if g:
+            ref = np.array([g["sectors"]["%d,%d" % s]["evals"][0] for s in sectors])
+    out = {"workload": "kanamori_Ns12_3orb_9bath_all169_sectors", "sum_D": sum_d, "setup_s": round(tset, 3)}
+    runs = (("keep8_of_20_reorth3", dict(tol=1e-7, max_basis=20, keep=8, reorth=3, max_iter=3000)),
+            ("basis60_cgs2", dict(tol=1e-7, max_basis=60, reorth=2, max_iter=3000)))
+    E_main = None
+    for key, kw in runs:
+        opts = ed.options(**kw)
+        ed.lanczos_ground_batched(hs, opts, seed=seed)           # graph capture + tile tuning
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E, info = ed.lanczos_ground_batched(hs, opts, seed=seed)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        st = ed.batched_last_stats()
+        r = {"seconds": round(tb, 4), "steps": st["steps"], "restart_events": st["restart_events"],
+             "ms_per_step": round(1e3 * tb / max(st["steps"], 1), 4), "tile": st["tile"],
+             "algorithmic_GB": round(st["bytes"] / 1e9, 3),
+             "algorithmic_GBps": round(st["bytes"] / tb / 1e9, 1),
+             "frac_of_8TBps": round(st["bytes"] / tb / 8e12, 4),
+             "apply_equiv_GBps": round(8.0 * sum_d * st["steps"] / tb / 1e9, 1),
+             "iters_max": max(i["iters"] for i in info), "restarts_max": max(i["restarts"] for i in info),
+             "all_converged": all(i["converged"] for i in info), "options": kw}
+        if ref is not None:
+            r["max_rel_err_vs_oracle"] = float(np.max(np.abs(np.array(E) - ref) / np.maximum(1.0, np.abs(ref))))
+        out[key] = r
+        if E_main is None:
+            E_main = E
+            out["batched_s"] = r["seconds"]
+        log("batched 169 sectors %s: %.3f s, %d steps (%.3f ms/step), %.1f GB/s algorithmic" %
+            (key, tb, st["steps"], r["ms_per_step"], r["algorithmic_GBps"]))
+    opts = ed.options(tol=1e-7, max_basis=20, keep=8, reorth=3, max_iter=3000)
     Dmax = max(h.D for h in hs)
     ws = torch.empty(max(h.workspace_bytes(opts, 1) for h in hs), dtype=torch.uint8, device="cuda")
     v0 = torch.empty(Dmax, dtype=torch.float32, device="cuda")
@@ -352,43 +453,44 @@ def batched_bench():
         Es.append(e)
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
-    out = {"workload": "kanamori_Ns12_3orb_9bath_all169_sectors", "sum_D": int(sum(h.D for h in hs)),
-           "batched_s": round(tb, 4), "sequential_s": round(ts, 4), "speedup": round(ts / tb, 2),
-           "setup_s": round(tset, 3), "tile": int(ed._lib.ed_batched_last_tile()),
-           "all_converged": all(i["converged"] for i in info),
-           "max_abs_diff_batched_vs_sequential": float(np.max(np.abs(np.array(E) - np.array(Es))))}
-    gold = os.path.join(ROOT, "tests", "golden", "oracle_e0.json")
-    if os.path.exists(gold):
-        g = json.load(open(gold))["entries"].get("cfg3")
-        if g:
-            ref = np.array([g["sectors"]["%d,%d" % s]["evals"][0] for s in sectors])
-            out["max_rel_err_vs_oracle"] = float(np.max(np.abs(np.array(E) - ref) / np.maximum(1.0, np.abs(ref))))
-    log("batched 169 sectors: %.3f s (sequential %.3f s)" % (tb, ts))
+    out["sequential_s"] = round(ts, 4)
+    out["sequential_options"] = "same as keep8_of_20_reorth3, one sector after another"
+    out["speedup"] = round(ts / out["batched_s"], 2)
+    out["max_abs_diff_batched_vs_sequential"] = float(np.max(np.abs(np.array(E_main) - np.array(Es))))
+    log("batched 169 sectors: %.3f s (sequential %.3f s)" % (out["batched_s"], ts))
     return out
 
 
 def pmc_pass(args):
-    """Workload for rocprofv3 counter runs: the tuned FP32 apply, then plain
-    device copies of x (4 D bytes read, 4 D bytes written) to calibrate the
-    counters against a kernel whose traffic is known."""
+    """Workload for rocprofv3 counter runs: K applies of each schedule named in
+    --schedules (default: the tuned one) in the --order basis order, then K
+    plain device copies of x (4 D bytes read, 4 D bytes written) to calibrate
+    the counters against a kernel whose traffic is known."""
     import torch
     from paper_1004_3354_amd import ed
     cfg = 2 if args.workload == "ns15" else 4
     phys, nn, b, H, _ = setup(cfg, ed.ED_FP32)
+    HH = (H.grouped() or H) if args.order == "grouped" else H
     x = torch.empty(b.D, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     ed.fill_random(x, 12345, 0)
-    H.apply(x, y)
+    names = [v for v in args.schedules.split(",") if v] if args.schedules else []
+    ids = [v for v in range(ed.variant_count()) if ed.variant_name(v) in names]
+    if not ids:
+        HH.apply(x, y)
+        ids = [HH.current_variant()]
     torch.cuda.synchronize()
-    log("pmc-pass %s D=%d schedule %s" % (args.workload, b.D, ed.variant_name(H.current_variant())))
-    for _ in range(args.steps):
-        H.apply(x, y)
-    torch.cuda.synchronize()
+    for v in ids:
+        log("pmc-pass %s D=%d %s order, schedule %s" % (args.workload, b.D, args.order, ed.variant_name(v)))
+        for _ in range(args.steps):
+            HH.apply_variant(v, x, y)
+        torch.cuda.synchronize()
     for _ in range(args.steps):
         y.copy_(x)
     torch.cuda.synchronize()
-    print(json.dumps({"workload": args.workload, "D": b.D, "schedule": ed.variant_name(H.current_variant()),
-                      "steps": args.steps, "copy_bytes_each_way": 4 * b.D}), flush=True)
+    print(json.dumps({"workload": args.workload, "D": b.D, "order": args.order,
+                      "schedules": [ed.variant_name(v) for v in ids], "steps": args.steps,
+                      "copy_bytes_each_way": 4 * b.D}), flush=True)
 
 
 def apply_leg(cfg, prec, steps, warmup=2):
@@ -451,7 +553,13 @@ def lowest_leg(cfg, precs, k, opts_kw, seed_idx):
                     "levels": [float(e) for e in ev], "iters": [i["iters"] for i in infos],
                     "residual": [i["residual"] for i in infos],
                     "kato_temple_lower": [i["e_lower"] for i in infos], "converged": all(i["converged"] for i in infos),
-                    "max_basis": kw.get("max_basis"), "keep": kw.get("keep"), "setup_s": round(tset, 3)}
+                    "max_basis": kw.get("max_basis"), "keep": kw.get("keep"), "setup_s": round(tset, 3),
+                    "e0_step_roofline": step_roofline(infos[0], t1 - t0)}
+        if k > 1:
+            tot = dict(infos[0])
+            tot["traffic"] = sum(i["traffic"] for i in infos)
+            tot["iters"] = sum(i["iters"] for i in infos)
+            out[key]["all_levels_step_roofline"] = step_roofline(tot, t2 - t0)
         log("N_s=%d %s: E0 %.12f in %.3f s, %d levels in %.3f s" % (phys["Ns"], key, ev[0], t1 - t0, k, t2 - t0))
         del ws, evecs, v0, H, b
         torch.cuda.empty_cache()
@@ -482,7 +590,19 @@ def main():
                     help="sector used by --pmc-pass")
     ap.add_argument("--order", choices=["grouped", "rank"], default="grouped",
                     help="basis order of the --pmc-pass apply")
+    ap.add_argument("--schedules", default="", help="comma-separated schedule names for --pmc-pass")
+    ap.add_argument("--summarize-stats", metavar="KERNEL_STATS_CSV",
+                    help="print the per-kernel summary of a rocprofv3 --stats run and exit (no GPU)")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "PMC_PASS_LOG", "WORKLOAD"),
+                    help="print HBM bytes per apply from two --pmc-pass counter runs and exit (no GPU)")
     args = ap.parse_args()
+    if args.summarize_stats:
+        for n, c, a in summarize_stats(args.summarize_stats)[:25]:
+            print("%6d  %12.2f us  %s" % (c, a / 1e3, n[:120]))
+        return
+    if args.summarize_traffic:
+        print(json.dumps(summarize_traffic(*args.summarize_traffic), indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sector is held by a single MI355X and no multi-GPU "
               "path is built; run with --gpus 1", file=sys.stderr)

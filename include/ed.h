@@ -207,8 +207,11 @@ void ed_ham_free(ed_ham_t h);
  * Section 4 and the Anderson impurity of Eq. 2 with their bath levels attached
  * to one orbital each -- ed_ham_create also builds the same operator in a
  * grouped basis order: the states of each spin ordered by component
- * (components by their lowest rank), by rank within a component.  Every hop
- * then stays inside an (up component x down component) tile of the vector.
+ * (components by their lowest rank); within a component, states with more
+ * moves first, then by rank (so the tile kernels' hop-table slices hold states
+ * of similar hop counts), or by rank alone when the environment variable
+ * ED_GROUP_ORDER=rank is set at ed_ham_create.  Every hop then stays inside an
+ * (up component x down component) tile of the vector.
  * The solvers iterate in that order by default (ed_lanczos_opts.layout) and
  * convert their vectors at the boundary; these calls expose it.
  *
@@ -276,6 +279,10 @@ typedef struct {
     double e_lower;       /* Kato-Temple lower bound E - residual^2 / (eta - E);
                              [e_lower, E] holds the eigenvalue when eta is a true
                              lower bound on the next one; NaN if eta <= E         */
+    double traffic;       /* algorithmic bytes the run's kernels moved: per H.v x read
+                             and y written; per Gram-Schmidt pass the projected
+                             vectors read and Y read and written; every restart,
+                             Ritz, normalisation and refinement pass likewise      */
 } ed_info;
 
 /* Fill opts with the defaults above. */
@@ -420,27 +427,39 @@ void ed_levels_free(ed_levels_t L);
  * of Section 3.2 trace the load imbalance of equal-size splits of the matrix to
  * rows with unequal work: here each sector's share of every batched kernel is
  * sized by its own dimension and row work): one restarted Lanczos per
- * sector, all advanced in lockstep; every step is a fixed sequence of batched
- * kernels over all sectors whose step index lives in device memory, captured
- * once in a hipGraph and replayed, with converged sectors masked off on the
- * device.  The apply runs over row tiles of about T output elements per
- * workgroup, T picked on the first step by timing candidates
- * (ED_BATCH_TILE=<T> forces one; ed_batched_last_tile reports the choice).
- * hs: nsec handles of one precision on one GPU.  v0s: optional HOST array of
- * nsec DEVICE start vectors (NULL: sector i starts from the SplitMix64 normal
- * stream seed + i).  E0: HOST [nsec] lowest eigenvalue per sector (FP64
- * Rayleigh quotient of the Ritz vector when opts->refine).  info: HOST [nsec]
- * or NULL.  ws: DEVICE workspace of at least ed_batched_workspace_bytes.
- * max_basis = 0 gives 60 vectors per sector.
- * Synchronous.  ED_ENOCONV if some sector hit max_iter (all E0 still written).
- * The batch restarts explicitly and runs CGS2 (opts->keep is ignored and
- * reorth = 3 runs as 2). */
+ * sector, every running sector advanced by the same replayed step -- a fixed
+ * sequence of batched kernels captured once in a hipGraph -- while each
+ * sector keeps its own step index, so sectors converge (masked off on the
+ * device), fill their basis and restart independently.  A sector whose basis
+ * is full waits until the host restarts it (at most check_every steps later):
+ * implicitly with opts->keep vectors when keep > 0 (exact shifts, as
+ * ed_lanczos_ground), else from its Ritz vector; all waiting sectors restart in
+ * one batched combination.  opts->reorth 0..3 as for ed_lanczos_ground.  The
+ * apply runs over row tiles of about T output elements per workgroup, T picked
+ * on the first step by timing candidates (ED_BATCH_TILE=<T> forces one); the
+ * vector kernels run over chunks of at most 8192 elements of one sector.
+ * hs: nsec handles of one precision on one GPU, each with D < 2^31.  v0s:
+ * optional HOST array of nsec DEVICE start vectors (NULL: sector i starts from
+ * the SplitMix64 normal stream seed + i).  E0: HOST [nsec] lowest eigenvalue per
+ * sector (FP64 Rayleigh quotient of the Ritz vector when opts->refine).  info:
+ * HOST [nsec] or NULL (iters: steps of that sector; gap_lower, e_lower: NaN).  ws: DEVICE
+ * workspace of at least ed_batched_workspace_bytes.  max_basis = 0 gives 60
+ * vectors per sector (at most 1000; keep is used with at most 256).  max_iter
+ * bounds the replayed steps.  Synchronous.  ED_ENOCONV if some sector was
+ * still unconverged at max_iter (all E0 still written). */
 ed_status ed_batched_workspace_bytes(int nsec, const ed_ham_t *hs, const ed_lanczos_opts *opts,
                                      size_t *bytes);
 ed_status ed_lanczos_ground_batched(int nsec, const ed_ham_t *hs, const ed_lanczos_opts *opts,
                                     const void *const *v0s, uint64_t seed, void *ws, size_t ws_bytes,
                                     double *E0, ed_info *info, void *stream);
 int64_t ed_batched_last_tile(void);
+/* Figures of the last batched run in this process (not thread-safe): steps =
+ * replayed graph steps, restart_events = batched restart launches, bytes =
+ * algorithmic bytes moved (per step and sector: x read, y written, and per
+ * projection pass the nv projected vectors read twice plus Y read twice and
+ * written once; per restart the inputs read and outputs written).  Any output
+ * may be NULL. */
+void ed_batched_last_stats(int64_t *steps, int64_t *restart_events, double *bytes);
 
 #ifdef __cplusplus
 }

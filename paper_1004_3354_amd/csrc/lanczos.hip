@@ -1024,6 +1024,8 @@ struct Solver {
     Work w;
     int nlock = 0;
     std::vector<double> lock_sig2;
+    double moved = 0.0;  // algorithmic bytes of the vector kernels launched so far
+    void count(double nvec) { moved += nvec * (double)h->D * (double)w.elem; }
 
     template <typename TX>
     void multidot(int vbeg, int nvec, const void *y) {
@@ -1039,6 +1041,7 @@ struct Solver {
         ED_LAUNCH_CHECK();
     }
     void dots(int vbeg, int nvec, const void *y, double *alpha, int jrel) {
+        count(nvec + 1);
         if (h->prec == ED_FP64) multidot<double>(vbeg, nvec, y);
         else multidot<float>(vbeg, nvec, y);
         k_finalize_dots_par<<<nvec, 256, 0, s>>>(w.partials, w.nblk, w.sig2 + vbeg, w.raw, w.gamma + vbeg, alpha,
@@ -1047,6 +1050,7 @@ struct Solver {
     }
     // both projections of one step from a single read of the basis (reorth = 3)
     void dots_gram(int nvec, const void *y, const void *z, double *alpha) {
+        count(nvec + 2);
         if (h->prec == ED_FP64)
             k_multidot_v4<double, 8, true><<<w.nblk, kRedBS, 0, s>>>((const double *const *)w.vp, nvec,
                                                                     (const double *)y, (const double *)z, h->D,
@@ -1062,10 +1066,12 @@ struct Solver {
         ED_LAUNCH_CHECK();
     }
     void update(int vbeg, int nvec, void *y, double *normp, const double *post = nullptr) {
+        count(nvec + 2);
         if (h->prec == ED_FP64) lincomb<double>(vbeg, w.gamma + vbeg, nvec, y, 0, 1.0, normp, post);
         else lincomb<float>(vbeg, w.gamma + vbeg, nvec, y, 0, 1.0, normp, post);
     }
     void combine(int vbeg, const double *coef, int nvec, void *out) {  // out = sum coef_i S_i
+        count(nvec + 1);
         if (h->prec == ED_FP64) lincomb<double>(vbeg, coef, nvec, out, 1, -1.0, nullptr, nullptr);
         else lincomb<float>(vbeg, coef, nvec, out, 1, -1.0, nullptr, nullptr);
     }
@@ -1080,6 +1086,7 @@ struct Solver {
     }
     // caller vector (rank order) -> workspace slot (the operator's order)
     void load_vector(const void *src, void *dst) {
+        count(2);
         if (flat) permute_vector(h, src, dst, 0, s);
         else ED_HIP(hipMemcpyAsync(dst, src, (size_t)h->D * w.elem, hipMemcpyDeviceToDevice, s));
     }
@@ -1093,6 +1100,7 @@ struct Solver {
     }
     // vector norm^2 of y via a one-vector multidot with pointer slot `idx`
     double norm2_sync(int idx, const void *y) {
+        count(1);
         if (h->prec == ED_FP64) multidot<double>(idx, 1, y);
         else multidot<float>(idx, 1, y);
         k_finalize_dots_par<<<1, 256, 0, s>>>(w.partials, w.nblk, nullptr, w.raw, nullptr, nullptr, 0);
@@ -1111,6 +1119,7 @@ struct Solver {
         }
         double n2 = norm2_sync(nlock, s0);
         if (!(n2 > 0.0) || !std::isfinite(n2)) fail(ED_EINVAL, "start vector is zero (or lies in the locked subspace)");
+        count(2);
         k_scale<<<grid_for(h->D, 256, 1 << 16), 256, 0, s>>>(s0, h->D, 1.0 / std::sqrt(n2), h->prec == ED_FP32);
         ED_LAUNCH_CHECK();
         n2 = norm2_sync(nlock, s0);
@@ -1141,6 +1150,7 @@ struct Solver {
         if (!ir_plan(al, be, sg, m, k, C, a2, b2, ev)) return false;
         const int nin = m + 1, nout = k + 1;
         ED_HIP(hipMemcpyAsync(w.rcoef, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        count(nin + nout);
         if (h->prec == ED_FP64)
             launch_restart_combine<double>((const double *const *)w.vp + nlock, w.rcoef, nin, nout, h->D, w.partials,
                                            w.nblk, s);
@@ -1195,6 +1205,7 @@ struct Solver {
         for (int j = 0; j < m; ++j) {
             void *Y = kr[j + 1];
             apply_launch(h, kr[j], Y, s);
+                count(2);
             const int nv = j + 1;
             if (o.reorth == 3) {
                 dots_gram(nv, Y, kr[j], w.alpha + j);
@@ -1263,6 +1274,7 @@ struct Solver {
         const int m = (int)std::min<int64_t>(w.m, h->D - nlock);
         const bool spans = (int64_t)m == h->D - nlock && o.reorth >= 2;
         ed_info inf{};
+        moved = 0.0;
         if (fresh >= 0) {
             k_fill<<<grid_for(h->D, 256, 1 << 16), 256, 0, s>>>(w.slots[0], h->D, (uint64_t)fresh, 1,
                                                                h->prec == ED_FP32 ? 1 : 0);
@@ -1290,6 +1302,7 @@ struct Solver {
             for (; j < m; ++j) {
                 void *Y = kr[j + 1];
                 apply_launch(h, kr[j], Y, s);
+                count(2);
                 const int nv = nlock + j + 1;
                 int vb = 0, nvec = nv;
                 if (o.reorth == 0 && j >= 2) {  // three-term recurrence by projection on S_{j-1}, S_j
@@ -1387,6 +1400,7 @@ struct Solver {
         ED_HIP(hipStreamSynchronize(s));
         const double n2 = norm2_sync(nlock, out);
         if (!(n2 > 0.0)) fail(ED_EDEVICE, "Ritz vector has zero norm");
+        count(2);
         k_scale<<<grid_for(h->D, 256, 1 << 16), 256, 0, s>>>(out, h->D, 1.0 / std::sqrt(n2), h->prec == ED_FP32);
         ED_LAUNCH_CHECK();
         inf.iters = total;
@@ -1395,6 +1409,7 @@ struct Solver {
         double rq = theta, rr = resid;
         if (o.refine) {
             rayleigh_fp64(h, out, &rq, &rr, s);
+            count(2);
             inf.residual = rr;
             inf.rq_fp64 = rq;
             *E = rq;
@@ -1405,6 +1420,7 @@ struct Solver {
         }
         ED_HIP(hipStreamSynchronize(s));
         kato_temple(jlast, rq, rr, &inf);
+        inf.traffic = moved;
         if (info) *info = inf;
         return converged ? ED_OK : ED_ENOCONV;
     }

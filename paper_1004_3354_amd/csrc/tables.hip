@@ -10,6 +10,8 @@
 // are sorted by target rank.  Because h is symmetric the same table serves the
 // gather (pull) form of the product.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 #include <cmath>
 #include <map>
 #include <tuple>
@@ -804,11 +806,16 @@ static int component_order(const SpinTab &t, std::vector<int32_t> &perm, std::ve
     for (int64_t r = 0; r < dim; ++r) perm[start[root[r]]++] = (int32_t)r;
     // within a component: more hops first, then by rank, so that runs of
     // consecutive positions (the slices of the tile kernels' hop tables) hold
-    // states with similar hop counts and little padding
-    for (size_t c = 0; c + 1 < comp_off.size(); ++c)
-        std::stable_sort(perm.begin() + comp_off[c], perm.begin() + comp_off[c + 1], [&](int32_t a, int32_t b) {
-            return off[a + 1] - off[a] > off[b + 1] - off[b];
-        });
+    // states with similar hop counts and little padding.  ED_GROUP_ORDER=rank
+    // keeps rank order inside a component instead, which keeps the partners of
+    // moves confined to the lowest sites (the four-fermion terms of the
+    // impurity models) in the same relative order as their sources.
+    const char *env = std::getenv("ED_GROUP_ORDER");
+    if (!(env && std::strcmp(env, "rank") == 0))
+        for (size_t c = 0; c + 1 < comp_off.size(); ++c)
+            std::stable_sort(perm.begin() + comp_off[c], perm.begin() + comp_off[c + 1], [&](int32_t a, int32_t b) {
+                return off[a + 1] - off[a] > off[b + 1] - off[b];
+            });
     return (int)comp_off.size() - 1;
 }
 

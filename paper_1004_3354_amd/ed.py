@@ -56,7 +56,8 @@ class ed_lanczos_opts(ctypes.Structure):
 class ed_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("basis_used", ctypes.c_int32), ("residual", ctypes.c_double), ("ritz", ctypes.c_double),
-                ("rq_fp64", ctypes.c_double), ("gap_lower", ctypes.c_double), ("e_lower", ctypes.c_double)]
+                ("rq_fp64", ctypes.c_double), ("gap_lower", ctypes.c_double), ("e_lower", ctypes.c_double),
+                ("traffic", ctypes.c_double)]
 
     def as_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -127,6 +128,8 @@ if hasattr(_lib, "ed_lanczos_ground_batched"):
     _sig("ed_lanczos_ground_batched", ctypes.c_int, [ctypes.c_int, _p, ctypes.POINTER(ed_lanczos_opts), _p,
                                                      ctypes.c_uint64, _p, ctypes.c_size_t, _p, _p, _p])
     _sig("ed_batched_last_tile", ctypes.c_int64, [])
+    _sig("ed_batched_last_stats", None, [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_double)])
 
 
 def _check(st: int, ok=(ED_OK,)):
@@ -417,6 +420,17 @@ def lanczos_ground_batched(hams: Sequence[Hamiltonian], opts=None, seed: int = 0
                                         E.ctypes.data_as(_p), ctypes.cast(infos, _p), _stream(stream))
     _check(st, (ED_OK, ED_ENOCONV) if allow_noconv else (ED_OK,))
     return E, [i.as_dict() for i in infos]
+
+
+def batched_last_stats():
+    """Figures of the last batched run in this process: graph-replayed steps,
+    restart events, apply tile size and algorithmic bytes moved (x read and y
+    written per step, the projection window read twice and Y read twice and
+    written once per pass, and every restart's inputs and outputs)."""
+    steps, ev, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    _lib.ed_batched_last_stats(ctypes.byref(steps), ctypes.byref(ev), ctypes.byref(nb))
+    return {"steps": steps.value, "restart_events": ev.value, "tile": int(_lib.ed_batched_last_tile()),
+            "bytes": nb.value}
 
 
 def apply_ladder(src: "Hamiltonian", dst: "Hamiltonian", spin: int, site: int, dagger: bool, x, y, stream=None):

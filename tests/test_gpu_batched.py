@@ -101,3 +101,56 @@ def test_batched_restarts_small_basis():
     assert any(i["restarts"] > 0 for i in info)
     for sec, e in zip(sectors, E):
         assert abs(e - gold[sec]) / max(1.0, abs(gold[sec])) <= 1e-6, (sec, e, gold[sec])
+
+
+def test_batched_implicit_restart_gram_all_sectors_vs_oracle():
+    """keep = 8 of 20 stored vectors (exact-shift implicit restarts) with both
+    projections per basis read (reorth = 3), all 169 sectors, FP32-mixed."""
+    ed = gpu_ed()
+    phys, sectors = wl.config(3)
+    hs = _hams(phys, sectors, ed.ED_FP32)
+    E, info = ed.lanczos_ground_batched(hs, ed.options(tol=1e-7, max_basis=20, keep=8, reorth=3, max_iter=3000),
+                                        seed=wl.start_vector_seed(3))
+    st = ed.batched_last_stats()
+    gold = _gold()
+    worst = 0.0
+    for (sec, e, inf) in zip(sectors, E, info):
+        assert inf["converged"] == 1, (sec, inf)
+        r = abs(e - gold[sec]) / max(1.0, abs(gold[sec]))
+        worst = max(worst, r)
+        assert r <= 1e-6, (sec, e, gold[sec])
+    assert any(i["restarts"] > 0 for i in info)
+    assert st["steps"] >= max(i["iters"] for i in info) and st["restart_events"] > 0
+    # every step moves at least x and y of the largest sector
+    assert st["bytes"] >= 8.0 * max(h.D for h in hs) * max(i["iters"] for i in info)
+    print("keep 8 / 20, reorth 3: worst relative error %.2e, %d steps, %d restart events" %
+          (worst, st["steps"], st["restart_events"]))
+
+
+@pytest.mark.parametrize("reorth", [0, 1, 3])
+def test_batched_reorth_modes_fp64_subset(reorth):
+    """The three-term recurrence (0), one full pass (1) and the Gram read (3),
+    explicit restarts from a 40-vector basis, against the oracle in FP64."""
+    ed = gpu_ed()
+    phys, _ = wl.config(3)
+    sectors = [(0, 0), (1, 0), (3, 2), (6, 6), (5, 7), (12, 0), (4, 9)]
+    hs = _hams(phys, sectors, ed.ED_FP64)
+    E, info = ed.lanczos_ground_batched(hs, ed.options(tol=1e-10, max_basis=40, reorth=reorth, max_iter=3000),
+                                        seed=11)
+    gold = _gold()
+    for sec, e, inf in zip(sectors, E, info):
+        assert inf["converged"] == 1, (sec, inf)
+        assert abs(e - gold[sec]) / max(1.0, abs(gold[sec])) <= 1e-9, (reorth, sec, e, gold[sec])
+
+
+def test_batched_implicit_restart_fp64_matches_explicit():
+    """FP64, keep = 6 of 16: the same eigenvalues as explicit restarts, to 1e-10."""
+    ed = gpu_ed()
+    phys, _ = wl.config(3)
+    sectors = [(6, 6), (5, 6), (2, 9), (7, 7)]
+    hs = _hams(phys, sectors, ed.ED_FP64)
+    E1, i1 = ed.lanczos_ground_batched(hs, ed.options(tol=1e-11, max_basis=16, keep=6, max_iter=4000), seed=2)
+    E2, _ = ed.lanczos_ground_batched(hs, ed.options(tol=1e-11, max_basis=16, max_iter=4000), seed=2)
+    assert any(i["restarts"] > 0 for i in i1)
+    for a, b in zip(E1, E2):
+        assert abs(a - b) <= 1e-10 * max(1.0, abs(b))

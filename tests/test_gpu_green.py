@@ -16,10 +16,13 @@ at 400 levels it is below 1e-13.
 
 Tolerances (relative to max |G| over the frequencies): FP64 1e-9, from a
 ground vector with residual ~1e-13 and continued fractions of well under 100
-levels; FP32-mixed 1e-4, from an FP32 ground vector whose components carry
-relative errors of a few 1e-7 amplified by the Krylov recursion in FP32
-(the Green function is linear in the squared ladder weights and continuous in
-the coefficients; the measured error is about ten times below this bar).
+levels; FP32-mixed 1e-5, from an FP32 ground vector whose components carry
+relative errors of a few 1e-7 amplified by the Krylov recursion in FP32 (the
+Green function is linear in the squared ladder weights and continuous in the
+coefficients).  The largest FP32 error measured over these cases is 3.0e-6
+(kan6_33, spin up, every reorthogonalisation mode; the inputs are seeded and
+the reductions run in a fixed order, so it is the same on every run): the bar
+is that error times 3.3.
 """
 import numpy as np
 import pytest
@@ -33,7 +36,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 ZM = 1j * np.pi * (2 * np.arange(8) + 1) / 10.0            # Matsubara points, beta = 10
 ZR = np.linspace(-4.0, 4.0, 9) + 0.15j                      # near the real axis
-TOL = {0: 1e-9, 1: 1e-4}
+TOL = {0: 1e-9, 1: 1e-5}
 
 
 def _vec(n, prec, seed):
@@ -176,6 +179,8 @@ def test_green_function_vs_lehmann(name, phys, nn, spin, site, prec, reorth):
     for part in ("particle", "hole"):
         assert abs(info[part]["weight"] - rinfo["weights"][part]) <= TOL[prec], (part, info[part], rinfo["weights"])
     err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    wmax = max(abs(info[p]["weight"] - rinfo["weights"][p]) for p in ("particle", "hole"))
+    print("[green-err] lehmann %s prec %d reorth %d: G %.2e, weights %.2e" % (name, prec, reorth, err, wmax))
     assert err <= TOL[prec], (name, err)
 
 
@@ -297,6 +302,7 @@ def test_green_thermal_full_spectrum_vs_eq3(prec):
                                   cutoff=0.0, m=64, precision=prec, opts=_thermal_opts(prec))
         assert det["edge"] == [] and len(det["levels"]) == 4 ** ns
         err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+        print("[green-err] thermal-full prec %d beta %g: G %.2e" % (prec, beta, err))
         assert err <= TOL[prec], (beta, spin, site, err)
 
 
@@ -367,4 +373,6 @@ def test_green_thermal_lowest_levels_vs_eq3(prec):
     delta = max(0.0, 1.0 - share)
     assert len(kept) >= 40
     bar = TOL[prec] * np.max(np.abs(ref))
+    print("[green-err] thermal-K40 prec %d: G %.2e of max|G|, truncation bound %.2e" %
+          (prec, np.max(np.abs(g - ref)) / np.max(np.abs(ref)), 2.0 * delta / np.min(ZM.imag) / np.max(np.abs(ref))))
     assert np.max(np.abs(g - ref)) <= 2.0 * delta / np.min(ZM.imag) + bar, (np.max(np.abs(g - ref)), delta)
