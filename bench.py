@@ -95,11 +95,14 @@ def summarize_traffic(fetch_csv, write_csv, info_json, workload):
         v = _per_dispatch(path, counter)
         copy = [x for n, l in v.items() if "copy" in n.lower() or "elementwise" in n.lower() for x in l]
         copy = sorted(copy)[-steps:]
-        apply_names = [n for n in v if any(k in n for k in APPLY_KERNELS)]
-        per_launch = 0.0
-        for n in apply_names:  # the last `steps` dispatches of each apply kernel are the timed ones
-            l = sorted(v[n])[-steps:]
-            per_launch += sum(c for _, c in l) / len(l)
+        # the timed applies are the last dispatches of apply kernels (the tuning
+        # run of every schedule comes before them): K kernels per apply, the K
+        # names seen among the last `steps` apply dispatches
+        disp = sorted((did, n, c) for n, l in v.items() if any(k in n for k in APPLY_KERNELS) for did, c in l)
+        kpa = len({n for _, n, _ in disp[-steps:]})
+        timed = disp[-kpa * steps:]
+        apply_names = sorted({n for _, n, _ in timed})
+        per_launch = sum(c for _, _, c in timed) / steps
         copy_kib = sum(c for _, c in copy) / max(len(copy), 1)
         factor = (cb / 1024.0) / copy_kib if copy_kib > 0 else float("nan")
         res[counter] = {"apply_kib_per_launch": per_launch, "copy_kib": copy_kib, "factor": factor,
@@ -108,7 +111,8 @@ def summarize_traffic(fetch_csv, write_csv, info_json, workload):
     return {workload: {"source_hash": kernel_source_hash(), "bytes_per_launch": total,
                        "fetch_bytes": res["FETCH_SIZE"]["bytes"], "write_bytes": res["WRITE_SIZE"]["bytes"],
                        "fetch_factor": res["FETCH_SIZE"]["factor"], "write_factor": res["WRITE_SIZE"]["factor"],
-                       "algorithmic_bytes": 8 * info["D"], "schedule": info["schedule"],
+                       "algorithmic_bytes": 8 * info["D"],
+                       "schedule": info.get("schedule") or ",".join(info.get("schedules", [])),
                        "kernels": res["FETCH_SIZE"]["kernels"]}}
 
 

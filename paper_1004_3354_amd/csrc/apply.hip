@@ -1225,11 +1225,15 @@ __global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
                 }
             }
         }
-        // four-fermion terms: partners in other components, from memory
+        // four-fermion terms: partners in other components, from memory.  The
+        // four gathers of a term are issued unconditionally (a column without a
+        // partner reads the partner row's first element and adds zero), so they
+        // are in flight together instead of one branch and one wait each.
         if (a.nx) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (r >= nr) break;
+#pragma unroll 2
                 for (int k = 0; k < nxl[r]; ++k) {
                     const TX *src = a.x + (uint32_t)x_src[r][k] * ddn;
                     const TA am = x_amp[r][k];
@@ -1242,11 +1246,13 @@ __global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
 #pragma unroll
                         for (int j = 0; j < 4; ++j) m[j] = cl + j < wl ? mp[j] : -1;
                     }
+                    TA v[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] = (TA)src[m[j] >= 0 ? ((uint32_t)m[j] >> 1) : 0u];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        if (m[j] < 0) continue;
-                        const TA v = (TA)src[(uint32_t)m[j] >> 1];
-                        acc[r][j] += (m[j] & 1) ? -am * v : am * v;
+                        const TA t = (m[j] & 1) ? -am * v[j] : am * v[j];
+                        acc[r][j] += m[j] >= 0 ? t : (TA)0;
                     }
                 }
             }
