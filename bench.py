@@ -118,11 +118,10 @@ def summarize_traffic(fetch_csv, write_csv, info_json, workload):
 
 def schedule_kernels(name):
     """Kernels one apply launches under a schedule (by schedule-name prefix)."""
-    for pre, k in (("rtg_", "k_rt (group-aligned tiles)"), ("rtp_", "k_rt (packed group tiles)"),
-                   ("rtb_", "k_rt (bond-ordered table)"), ("rt2_", "k_rt row pass + k_upb band pass"),
+    for pre, k in (("gt2_", "k_gtile row pass + k_upt band pass"), ("gt_", "k_gtile"),
+                   ("grp2_", "k_rt (grouped tiles) + k_upt band pass"), ("grp_", "k_rt (grouped tiles)"),
                    ("rt_", "k_rt"), ("csx_", "k_cs row pass + k_upb band pass"),
-                   ("cstp_", "k_cs + k_csb"), ("cs_", "k_cs"), ("tppk_", "k_apply + k_apply_band"),
-                   ("tp_", "k_apply + k_apply_band"), ("rwpk_", "k_apply (packed table)"), ("rw_", "k_apply")):
+                   ("rwpk_", "k_apply (packed table)"), ("rw_", "k_apply")):
         if name.startswith(pre):
             return k
     return name

@@ -1065,7 +1065,7 @@ __global__ __launch_bounds__(BS) void k_upt(ApplyArgs<TX, TA> a) {
 // (diagonal = e_up + e_dn + T[(c_up << fk) | c_dn]); otherwise it is a uniform
 // on-site U, U0 popc(s_up & s_dn & umask), and nothing else.
 template <typename TX, typename TA, int R, int BS, bool UPX, bool FOLD>
-__global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
+__device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
     using RVt = typename RV<TX, R>::t;
     using V = typename V4<TX>::t;
     constexpr int UL = 32, XL = 16;
@@ -1274,6 +1274,11 @@ __global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
     }
 }
 
+template <typename TX, typename TA, int R, int BS, bool UPX, bool FOLD>
+__global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
+    gtile_body<TX, TA, R, BS, UPX, FOLD>(a);
+}
+
 // ---------------------------------------------------------- variant table --
 // kind 0: single pass.  kind 1: two passes (row-local, then banded up spin).
 struct Variant {
@@ -1315,6 +1320,9 @@ static const Variant kVariants[] = {
     {12, 2, 512, 8192, "gt_r2_w8192"},      {12, 4, 512, 8192, "gt_r4_w8192"},
     // the same as the row pass of two passes, with the band pass of H_up (x) 1
     {13, 2, 512, 8192, "gt2_r2_w8192_band128", 0, 32}, {13, 8, 256, 1024, "gt2_r8_w1024_band128", 0, 32},
+    // lean tile kernel, two rows or one row per item, smaller workgroups
+    {12, 2, 256, 1024, "gt_r2_w1024"},      {12, 2, 128, 1024, "gt_r2_w1024_b128"},
+    {12, 1, 512, 8192, "gt_r1_w8192"},
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static constexpr int64_t kDynBudget = 163840 - 8192;  // LDS left for the staged x block
@@ -1938,6 +1946,9 @@ static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipSt
             launch_gtile<TX, TA, 8, 256, false>(h, a, 1024, s);
             launch_upt<TX, TA>(h, a, 128, V.rw, s);
             break;
+        case 31: launch_gtile<TX, TA, 2, 256>(h, a, 1024, s); break;
+        case 32: launch_gtile<TX, TA, 2, 128>(h, a, 1024, s); break;
+        case 33: launch_gtile<TX, TA, 1, 512>(h, a, 8192, s); break;
         default: fail(ED_EINVAL, "bad apply variant %d", v);
     }
 }
