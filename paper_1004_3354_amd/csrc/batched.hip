@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <thread>
 #include <vector>
 
 #include "ed_internal.h"
@@ -624,19 +625,26 @@ __global__ __launch_bounds__(256) void kb_restart_fin(BState st, BDims dm) {
     }
 }
 
-// per sector RQ from the apply partials of its tiles
-__global__ void kb_fin_rq(const ATile *tiles, int ntiles, const double *tpart, int nsec, double *out) {
-    // one thread per sector, fixed order over tiles (tiles are grouped by sector)
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsec) return;
+// per sector RQ from the apply partials of its tiles, which are contiguous
+// (tiles [tfirst[s], tfirst[s] + tcount[s])): one wave per sector, fixed order
+__global__ __launch_bounds__(64) void kb_fin_rq(const int *tfirst, const int *tcount, const double *tpart,
+                                                double *out) {
+    const int s = blockIdx.x;
+    const int t0 = tfirst[s], n = tcount[s];
     double a = 0.0, b = 0.0;
-    for (int t = 0; t < ntiles; ++t)
-        if (tiles[t].sec == s) {
-            a += tpart[2 * t];
-            b += tpart[2 * t + 1];
-        }
-    out[2 * s] = a;
-    out[2 * s + 1] = b;
+    for (int t = threadIdx.x; t < n; t += 64) {
+        a += tpart[2 * (int64_t)(t0 + t)];
+        b += tpart[2 * (int64_t)(t0 + t) + 1];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if (threadIdx.x == 0) {
+        out[2 * s] = a;
+        out[2 * s + 1] = b;
+    }
 }
 
 // ------------------------------------------------------------------ host --
@@ -869,7 +877,6 @@ static ed_status run_batched(int nsec, const ed_ham_t *hs, const ed_lanczos_opts
     std::vector<double> h_al(S * dm.ms), h_be(S * dm.ms), h_sg(S * dm.ms), h_tri(S * dm.mt);
     std::vector<double> h_coef(S * dm.mc, 0.0), h_a2b2(S * 34, 0.0);
     std::vector<int> h_nsteps(S), h_rnin(S), h_rnout(S), h_rmode(S);
-    std::vector<double> Cw, a2, b2, ev;
     double restart_bytes = 0.0;
     auto launch_restart = [&](int maxout) {
         for (int q = 0; q < nsec; ++q)
@@ -997,33 +1004,59 @@ static ed_status run_batched(int nsec, const ed_ham_t *hs, const ed_lanczos_opts
         }
         if (on == 0 && pend == 0) break;
         if (launches >= o.max_iter || pend == 0) continue;
-        // restart every sector whose basis is full
+        // restart every sector whose basis is full; the shift plans of the
+        // waiting sectors are independent host computations, spread over threads
         fetch_state();
         std::fill(h_rnout.begin(), h_rnout.end(), 0);
-        int maxout = 1;
-        for (int q = 0; q < nsec; ++q) {
-            if (act[q] != 2) continue;
-            ++restarts[q];
-            bool done = false;
-            if (o.keep > 0 && o.keep < m && h_nsteps[q] == m) {
+        std::vector<int> pending;
+        for (int q = 0; q < nsec; ++q)
+            if (act[q] == 2) {
+                ++restarts[q];
+                pending.push_back(q);
+            }
+        std::vector<char> implicit(pending.size(), 0);
+        auto plan_range = [&](size_t b, size_t e) {
+            std::vector<double> Cq, a2q, b2q, evq;
+            for (size_t t = b; t < e; ++t) {
+                const int q = pending[t];
+                if (!(o.keep > 0 && o.keep < m && h_nsteps[q] == m)) continue;
                 std::vector<double> al(h_al.begin() + (size_t)q * dm.ms, h_al.begin() + (size_t)q * dm.ms + m);
                 std::vector<double> be(h_be.begin() + (size_t)q * dm.ms, h_be.begin() + (size_t)q * dm.ms + m);
                 std::vector<double> sg(h_sg.begin() + (size_t)q * dm.ms, h_sg.begin() + (size_t)q * dm.ms + m + 1);
-                if (ir_plan(al, be, sg, m, o.keep, Cw, a2, b2, ev)) {
-                    std::copy(Cw.begin(), Cw.end(), h_coef.begin() + (size_t)q * dm.mc);
-                    double *ab = h_a2b2.data() + (size_t)q * 34;
-                    for (int i = 0; i < o.keep; ++i) {
-                        ab[i] = a2[i];
-                        ab[17 + i] = i + 1 < o.keep ? b2[i] : 0.0;
-                    }
-                    h_rnin[q] = m + 1;
-                    h_rnout[q] = o.keep + 1;
-                    h_rmode[q] = 2;
-                    maxout = std::max(maxout, o.keep + 1);
-                    done = true;
+                if (!ir_plan(al, be, sg, m, o.keep, Cq, a2q, b2q, evq)) continue;
+                std::copy(Cq.begin(), Cq.end(), h_coef.begin() + (size_t)q * dm.mc);
+                double *ab = h_a2b2.data() + (size_t)q * 34;
+                for (int i = 0; i < o.keep; ++i) {
+                    ab[i] = a2q[i];
+                    ab[17 + i] = i + 1 < o.keep ? b2q[i] : 0.0;
                 }
+                implicit[t] = 1;
             }
-            if (!done) ritz_request(q, 1);
+        };
+        const size_t nth = std::min<size_t>(std::min<size_t>(pending.size() / 4 + 1, 16),
+                                            std::max(1u, std::thread::hardware_concurrency()));
+        if (nth <= 1) {
+            plan_range(0, pending.size());
+        } else {
+            std::vector<std::thread> pool;
+            const size_t per = (pending.size() + nth - 1) / nth;
+            for (size_t k = 0; k < nth; ++k) {
+                const size_t b = k * per, e = std::min(pending.size(), b + per);
+                if (b < e) pool.emplace_back(plan_range, b, e);
+            }
+            for (auto &t : pool) t.join();
+        }
+        int maxout = 1;
+        for (size_t t = 0; t < pending.size(); ++t) {
+            const int q = pending[t];
+            if (implicit[t]) {
+                h_rnin[q] = m + 1;
+                h_rnout[q] = o.keep + 1;
+                h_rmode[q] = 2;
+                maxout = std::max(maxout, o.keep + 1);
+            } else {
+                ritz_request(q, 1);
+            }
         }
         launch_restart(maxout);
         ++events;
@@ -1052,9 +1085,19 @@ static ed_status run_batched(int nsec, const ed_ham_t *hs, const ed_lanczos_opts
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
         (void)hipGetLastError();
         kern<<<nt, kBBS, best_lds, s>>>(d_sec64, tiles.as<ATile>(), st.jcur, st.active, 0, tp.as<double>());
-        kb_fin_rq<<<(nsec + 63) / 64, 64, 0, s>>>(tiles.as<ATile>(), (int)nt, tp.as<double>(), nsec, rq);
+        std::vector<int> tfc((size_t)2 * nsec, 0);  // first tile, tile count per sector
+        for (size_t t = 0; t < best_tiles.size(); ++t) {
+            const int q = best_tiles[t].sec;
+            if (tfc[(size_t)nsec + q] == 0) tfc[q] = (int)t;
+            ++tfc[(size_t)nsec + q];
+        }
+        DevMem tfd;
+        tfd.alloc(tfc.size() * sizeof(int));
+        ED_HIP(hipMemcpyAsync(tfd.p, tfc.data(), tfc.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        kb_fin_rq<<<nsec, 64, 0, s>>>(tfd.as<int>(), tfd.as<int>() + nsec, tp.as<double>(), rq);
         ED_LAUNCH_CHECK();
         ED_HIP(hipMemcpyAsync(rqv.data(), rq, 2 * S * sizeof(double), hipMemcpyDeviceToHost, s));
+        ED_HIP(hipStreamSynchronize(s));  // before tp and tfd are released
     }
     ED_HIP(hipStreamSynchronize(s));
     // algorithmic bytes: per step x read + y write, and per projection pass the
