@@ -385,12 +385,13 @@ ed_status ed_boltzmann_weights(const double *E, int n, double beta, double cutof
  * thermal set the finite-temperature sum of Eq. 3 runs over (the paper's DMFT
  * iteration at N_s = 12 needs the 300 lowest states, end of Section 3.2).
  * Every sector's lowest level comes from one ed_lanczos_ground_batched run;
- * then, while some sector with levels left has its highest computed level at
- * or below the K-th lowest found so far, the sector whose highest computed
- * level is lowest gets more (k -> k + max(2, k/4), at most min(D, kmax)) by
- * ed_arnoldi_lowest_more on top of its converged vectors.  A sector's
- * uncomputed levels lie above its highest computed one, so no level that could
- * be among the K lowest is skipped.  Sector q's start vectors come from the
+ * then, in rounds, while some sector with levels left has its highest computed
+ * level at or below the K-th lowest found so far, the (up to 8) such sectors
+ * whose highest computed levels are lowest get more (k -> k + max(2, k/4), at
+ * most min(D, kmax)) by ed_arnoldi_lowest_more on top of their converged
+ * vectors, concurrently on streams of their own (one at a time when a sector is
+ * large).  A sector's uncomputed levels lie above its highest computed one, so
+ * no level that could be among the K lowest is skipped.  Sector q's start vectors come from the
  * SplitMix64 normal stream seed + q.  hs: nsec handles of one precision on one
  * GPU; opts: the Lanczos options of every run (max_basis = 0 plans each run
  * against the free device memory).  *out: a result handle that owns the

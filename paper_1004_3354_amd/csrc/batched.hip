@@ -86,7 +86,6 @@ static constexpr int kBBS = 256;
 static constexpr int kBatchBasisDefault = 60;  // basis per sector when max_basis = 0
 static constexpr int kBChunk = 8192;           // elements per vector-kernel workgroup
 static constexpr int kBRMaxC = 4400;           // restart coefficients held in LDS (nin * NO)
-static int64_t g_last_tile = 0;
 
 // Window of stored vectors the step projects against: all of S_0..S_j, or
 // S_{j-1}, S_j for the plain three-term recurrence (reorth = 0).

@@ -5,14 +5,16 @@
 //
 // Search: every sector's lowest level comes from one batched ground-state run;
 // then, as long as some sector that still has levels left has its highest
-// computed level at or below the K-th lowest level found so far, the sector
-// whose highest computed level is lowest gets more levels (restarted Lanczos
-// with explicit deflation against the converged vectors, continuing from
-// them).  A sector's uncomputed levels all lie above its highest computed one,
+// computed level at or below the K-th lowest level found so far, such sectors
+// get more levels (restarted Lanczos with explicit deflation against the
+// converged vectors, continuing from them), the few with the lowest highest
+// levels at once.  A sector's uncomputed levels all lie above its highest computed one,
 // so no level that could belong to the K lowest is skipped.  The vectors of
 // the levels found stay in device memory owned by the result handle.
 #include <algorithm>
 #include <cmath>
+#include <exception>
+#include <thread>
 #include <vector>
 
 #include "ed_internal.h"
@@ -66,62 +68,129 @@ static void lowest_levels(ed_levels_s *L, int nsec, const ed_ham_t *hs, int K, i
         if (st != ED_OK && st != ED_ENOCONV) fail(st, "%s", ed_last_error());
         for (int q = 0; q < nsec; ++q) L->energies[q] = {e0[q]};
     }
-    int64_t dmax = 1;
-    for (auto *h : L->hs) dmax = std::max(dmax, h->D);
     const size_t elem = L->hs[0]->prec == ED_FP64 ? 8 : 4;
-    DevMem v0, ws;
-    v0.alloc((size_t)dmax * elem);
-    auto extend = [&](int q, int k) {
+    // one extension: sector q from its nvec[q] converged levels to k, on the
+    // caller's stream with the caller's start-vector buffer and workspace
+    // (buffers are grown with headroom and replaced vectors are freed after the
+    // round: a device free waits for the whole device, which would serialise
+    // the concurrent extensions)
+    auto extend = [&](int q, int k, hipStream_t st, DevMem &v0, DevMem &ws, std::vector<DevMem *> &old) {
         ed_ham_s *h = L->hs[q];
         const int k0 = L->nvec[q];
+        if (v0.bytes < (size_t)h->D * elem) v0.alloc((size_t)h->D * elem);
         DevMem *ev = new DevMem();
         try {
             ev->alloc((size_t)k * (size_t)h->D * elem);
             if (k0 > 0)
                 ED_HIP(hipMemcpyAsync(ev->p, L->vecs[q]->p, (size_t)k0 * (size_t)h->D * elem, hipMemcpyDeviceToDevice,
-                                      s));
-            k_fill<<<grid_for(h->D, 256, 1 << 16), 256, 0, s>>>(v0.p, h->D, seed + (uint64_t)q, 1,
-                                                               h->prec == ED_FP32 ? 1 : 0);
+                                      st));
+            k_fill<<<grid_for(h->D, 256, 1 << 16), 256, 0, st>>>(v0.p, h->D, seed + (uint64_t)q, 1,
+                                                                h->prec == ED_FP32 ? 1 : 0);
             ED_LAUNCH_CHECK();
             const ed_lanczos_opts o = resolve(h, opts, k, false, device_budget());
             const size_t need = ws_needed(h, o, k, false);
-            if (ws.bytes < need) ws.alloc(need);
+            if (ws.bytes < need) ws.alloc(need + need / 2);
             std::vector<double> ev_h((size_t)k, 0.0);
             for (int i = 0; i < k0; ++i) ev_h[i] = L->energies[q][i];
-            const ed_status st = solve(h, k, &o, v0.p, ws.p, ws.bytes, ev_h.data(), ev->p, nullptr, s, k0);
-            if (st != ED_OK && st != ED_ENOCONV)
-                fail(st, "sector %d (D = %lld), %d levels: %s", q, (long long)h->D, k, ed_last_error());
+            const ed_status r = solve(h, k, &o, v0.p, ws.p, ws.bytes, ev_h.data(), ev->p, nullptr, st, k0);
+            if (r != ED_OK && r != ED_ENOCONV)
+                fail(r, "sector %d (D = %lld), %d levels: %s", q, (long long)h->D, k, ed_last_error());
             L->energies[q].assign(ev_h.begin(), ev_h.end());
         } catch (...) {
             delete ev;
             throw;
         }
-        delete L->vecs[q];
+        if (L->vecs[q]) old.push_back(L->vecs[q]);
         L->vecs[q] = ev;
         L->nvec[q] = k;
-        ++L->calls;
+    };
+    // Rounds: every sector that may still hold one of the K lowest levels (its
+    // highest computed level at or below the K-th lowest found so far, levels
+    // left) is a candidate; the lowest few candidates are extended at once,
+    // each on its own stream from its own host thread, so that the small
+    // sectors' kernels share the GPU.  Extending more sectors than the one
+    // with the lowest highest level can only compute levels that were not
+    // needed; no level that could be among the K lowest is skipped.
+    constexpr int kPar = 8;
+    std::vector<hipStream_t> streams(kPar);
+    for (auto &st : streams) ED_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    std::vector<DevMem> v0s(kPar), wss(kPar);
+    std::vector<std::vector<DevMem *>> olds(kPar);
+    auto free_old = [&]() {
+        for (auto &o : olds) {
+            for (DevMem *d : o) delete d;
+            o.clear();
+        }
     };
     std::vector<bool> capped((size_t)nsec, false);
-    while (true) {
-        const double T = kth_lowest(L->energies, K);
-        int best = -1;
-        for (int q = 0; q < nsec; ++q) {
-            const int have = (int)L->energies[q].size();
-            const int64_t lim = std::min<int64_t>(L->hs[q]->D, kmax);
-            if (highest(L->energies[q]) > T) continue;
-            if (have >= lim) {
-                if (have < L->hs[q]->D) capped[q] = true;
+    try {
+        while (true) {
+            const double T = kth_lowest(L->energies, K);
+            std::vector<int> cand;
+            for (int q = 0; q < nsec; ++q) {
+                const int have = (int)L->energies[q].size();
+                const int64_t lim = std::min<int64_t>(L->hs[q]->D, kmax);
+                if (highest(L->energies[q]) > T) continue;
+                if (have >= lim) {
+                    if (have < L->hs[q]->D) capped[q] = true;
+                    continue;
+                }
+                cand.push_back(q);
+            }
+            if (cand.empty()) break;
+            std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
+                return highest(L->energies[a]) < highest(L->energies[b]);
+            });
+            // concurrency only among sectors whose runs are small next to the device
+            int npar = std::min<int>(kPar, (int)cand.size());
+            for (int t = 0; t < npar; ++t)
+                if ((double)L->hs[cand[t]]->D * (double)elem * 64.0 > 2e9) {
+                    npar = 1;
+                    break;
+                }
+            auto target = [&](int q) {
+                const int k = L->nvec[q];
+                return (int)std::min<int64_t>(std::min<int64_t>(L->hs[q]->D, kmax), k + std::max(2, k / 4));
+            };
+            if (npar == 1) {
+                extend(cand[0], target(cand[0]), s, v0s[0], wss[0], olds[0]);
+                ++L->calls;
+                free_old();
                 continue;
             }
-            if (best < 0 || highest(L->energies[q]) < highest(L->energies[best])) best = q;
+            std::vector<std::exception_ptr> errs((size_t)npar);
+            std::vector<std::thread> pool;
+            for (int t = 0; t < npar; ++t)
+                pool.emplace_back([&, t] {
+                    try {
+                        DeviceGuard g(L->device);
+                        extend(cand[t], target(cand[t]), streams[t], v0s[t], wss[t], olds[t]);
+                    } catch (...) {
+                        errs[t] = std::current_exception();
+                    }
+                });
+            for (auto &th : pool) th.join();
+            free_old();
+            for (auto &e : errs)
+                if (e) std::rethrow_exception(e);
+            L->calls += npar;
         }
-        if (best < 0) break;
-        const int k = L->nvec[best];
-        extend(best, (int)std::min<int64_t>(std::min<int64_t>(L->hs[best]->D, kmax), k + std::max(2, k / 4)));
+    } catch (...) {
+        for (auto &st : streams) (void)hipStreamSynchronize(st);
+        for (auto &st : streams) (void)hipStreamDestroy(st);
+        free_old();
+        throw;
     }
+    for (auto &st : streams) ED_HIP(hipStreamSynchronize(st));
+    for (auto &st : streams) (void)hipStreamDestroy(st);
+    DevMem v0, ws;
     L->threshold = kth_lowest(L->energies, K);
     for (int q = 0; q < nsec; ++q)  // one-level sectors: the energy is known, the vector not yet
-        if (L->nvec[q] == 0 && L->energies[q][0] <= L->threshold) extend(q, 1);
+        if (L->nvec[q] == 0 && L->energies[q][0] <= L->threshold) {
+            extend(q, 1, s, v0, ws, olds[0]);
+            ++L->calls;
+        }
+    free_old();
     for (int q = 0; q < nsec; ++q) {
         if (capped[q]) L->capped.push_back(q);
         for (int i = 0; i < (int)L->energies[q].size(); ++i)
