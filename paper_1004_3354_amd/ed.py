@@ -20,6 +20,14 @@ if not os.path.exists(LIBPATH):
     raise ImportError("libedhip.so is not built (run __graft_entry__.build()); "
                       "there is no CPU fallback for the HIP path")
 
+# torch supplies the device memory and streams and ships its own HIP runtime
+# (same soname as the system one the library links): loading torch first makes
+# the library bind to that runtime instead of loading a second one
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = ctypes.CDLL(LIBPATH)
 
 ED_OK, ED_EINVAL, ED_ENOMEM, ED_EDEVICE, ED_ENOCONV, ED_EUNSUPPORTED = range(6)

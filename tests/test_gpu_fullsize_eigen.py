@@ -113,14 +113,14 @@ def test_hubbard4x4_u4_lowest4_fp32_vs_fp64(hubbard_u4_lowest):
 
 def test_ns18_lowest3_fp32():
     """N_s = 18, sector (9, 9): three lowest levels with a capped FP32 basis
-    (3 locked vectors + 16 basis vectors of 9.5 GB)."""
+    (3 locked vectors + 20 basis vectors of 9.5 GB, restarts keeping 10)."""
     ed = gpu_ed()
     phys, sectors = wl.config(4)
     (nu, nd), = sectors
     b = ed.Basis(18, nu, nd)
     H = ed.Hamiltonian(models.params_from_model(phys), b, ed.ED_FP32)
     v0 = _v0(H, 1, wl.start_vector_seed(4))
-    opts = ed.options(tol=1e-7, reorth=3, keep=8, max_basis=16, max_iter=3000)
+    opts = ed.options(tol=1e-7, reorth=3, keep=10, max_basis=20, max_iter=3000)
     evecs = torch.empty((3, H.D), dtype=torch.float32, device="cuda")
     ev, infos = H.lowest(1, v0, opts, evecs=evecs[:1])
     print("N_s=18 level 0: %.12f (%d steps)" % (ev[0], infos[0]["iters"]), flush=True)
