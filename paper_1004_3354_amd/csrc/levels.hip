@@ -89,7 +89,14 @@ static void lowest_levels(ed_levels_s *L, int nsec, const ed_ham_t *hs, int K, i
             ED_LAUNCH_CHECK();
             const ed_lanczos_opts o = resolve(h, opts, k, false, device_budget());
             const size_t need = ws_needed(h, o, k, false);
-            if (ws.bytes < need) ws.alloc(need + need / 2);
+            if (ws.bytes < need) {  // headroom for later extensions when the device has room for it
+                size_t fm = 0, tm = 0;
+                if (hipMemGetInfo(&fm, &tm) != hipSuccess) {
+                    (void)hipGetLastError();
+                    fm = 0;
+                }
+                ws.alloc(need + need / 2 <= fm / 2 ? need + need / 2 : need);
+            }
             std::vector<double> ev_h((size_t)k, 0.0);
             for (int i = 0; i < k0; ++i) ev_h[i] = L->energies[q][i];
             const ed_status r = solve(h, k, &o, v0.p, ws.p, ws.bytes, ev_h.data(), ev->p, nullptr, st, k0);
