@@ -766,9 +766,11 @@ static void validate(const ed_params *p, int ns) {
 // Connected components of one spin's move graph (the hop table, which also
 // holds the same-spin two-body moves) by union-find; the grouped order lists
 // the components by their lowest rank and each component's states by number
-// of hops (descending), then by rank.
+// of hops (descending), then by their occupation of the sites in `fmask` (the
+// sites the four-fermion terms move this spin between), then by rank.
 // Returns the number of components; perm[p] = rank at position p.
-static int component_order(const SpinTab &t, std::vector<int32_t> &perm, std::vector<int32_t> &comp_off) {
+static int component_order(const SpinTab &t, uint32_t fmask, std::vector<int32_t> &perm,
+                           std::vector<int32_t> &comp_off) {
     const int64_t dim = t.dim;
     std::vector<int32_t> off((size_t)dim + 1), tgt((size_t)std::max<int64_t>(t.nnz, 1));
     ED_HIP(hipMemcpy(off.data(), t.off.p, off.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -804,18 +806,27 @@ static int component_order(const SpinTab &t, std::vector<int32_t> &perm, std::ve
         }
     perm.assign((size_t)dim, 0);
     for (int64_t r = 0; r < dim; ++r) perm[start[root[r]]++] = (int32_t)r;
-    // within a component: more hops first, then by rank, so that runs of
-    // consecutive positions (the slices of the tile kernels' hop tables) hold
-    // states with similar hop counts and little padding.  ED_GROUP_ORDER=rank
-    // keeps rank order inside a component instead, which keeps the partners of
-    // moves confined to the lowest sites (the four-fermion terms of the
-    // impurity models) in the same relative order as their sources.
+    // within a component: more hops first, so that runs of consecutive
+    // positions (the slices of the tile kernels' hop tables) hold states with
+    // similar hop counts and little padding; then by the occupation of the
+    // four-fermion sites, so that a four-fermion move, which changes only those
+    // sites, maps each run of equal occupation onto a run of the partner
+    // component in the same order (its gathers read consecutive addresses);
+    // then by rank.  ED_GROUP_ORDER=hops drops the occupation key,
+    // ED_GROUP_ORDER=rank keeps plain rank order inside a component.
     const char *env = std::getenv("ED_GROUP_ORDER");
-    if (!(env && std::strcmp(env, "rank") == 0))
+    const bool by_rank = env && std::strcmp(env, "rank") == 0;
+    if (env && std::strcmp(env, "hops") == 0) fmask = 0u;
+    if (!by_rank) {
+        std::vector<uint32_t> st((size_t)dim);
+        if (dim > 0) ED_HIP(hipMemcpy(st.data(), t.states.p, (size_t)dim * sizeof(uint32_t), hipMemcpyDeviceToHost));
         for (size_t c = 0; c + 1 < comp_off.size(); ++c)
             std::stable_sort(perm.begin() + comp_off[c], perm.begin() + comp_off[c + 1], [&](int32_t a, int32_t b) {
-                return off[a + 1] - off[a] > off[b + 1] - off[b];
+                const int32_t ha = off[a + 1] - off[a], hb = off[b + 1] - off[b];
+                if (ha != hb) return ha > hb;
+                return (st[a] & fmask) < (st[b] & fmask);
             });
+    }
     return (int)comp_off.size() - 1;
 }
 
@@ -824,7 +835,12 @@ static int component_order(const SpinTab &t, std::vector<int32_t> &perm, std::ve
 static void build_twin(ed_ham_s *h, const ed_params *p, const BasisData &b) {
     std::vector<int32_t> perm[2], coff[2];
     int nc[2];
-    for (int s = 0; s < 2; ++s) nc[s] = component_order(h->sp[s], perm[s], coff[s]);
+    for (int s = 0; s < 2; ++s) {
+        uint32_t fmask = 0u;
+        for (size_t q = 0; q < h->sp[s].mv_src.size(); ++q)
+            fmask |= (1u << h->sp[s].mv_src[q]) | (1u << h->sp[s].mv_dst[q]);
+        nc[s] = component_order(h->sp[s], fmask, perm[s], coff[s]);
+    }
     if (nc[0] < 2 && nc[1] < 2) return;
     ed_ham_s *g = new ed_ham_s();
     try {

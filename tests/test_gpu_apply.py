@@ -304,9 +304,11 @@ def _components(off, tgt):
 @pytest.mark.parametrize("name,phys,sec_nn", GROUPED[:4], ids=[c[0] for c in GROUPED[:4]])
 def test_grouped_order_and_tables(name, phys, sec_nn):
     """The grouped order is a permutation that orders each component's states
-    by hop count (descending), then rank; every hop of the twin stays inside its component, and the
-    twin's hop table translated back to ranks is the oracle's (bit for bit,
-    per row as a set of (target, sign, amplitude))."""
+    by hop count (descending), then by the occupation of the sites the
+    four-fermion terms move that spin between, then rank; every hop of the twin
+    stays inside its component, and the twin's hop table translated back to
+    ranks is the oracle's (bit for bit, per row as a set of (target, sign,
+    amplitude))."""
     ed = gpu_ed()
     nup, ndn = sec_nn
     ns = int(phys["Ns"])
@@ -331,12 +333,21 @@ def test_grouped_order_and_tables(name, phys, sec_nn):
                         changed = True
             if not changed:
                 break
-        # contiguous components; inside each, more hops first, then ascending rank
+        # contiguous components; inside each, more hops first, then the
+        # four-fermion sites' occupation, then ascending rank
+        fmask = 0
+        for x in p["xterms"]:
+            if x[0] == orc.UD_GENERAL:   # c+_{i up} c+_{j dn} c_{l dn} c_{k up}: up k -> i, down l -> j
+                _, i, j, k, l, _ = x
+                fmask |= (1 << k) | (1 << i) if s == 0 else (1 << l) | (1 << j)
+            elif x[0] in (orc.SPIN_FLIP, orc.PAIR_HOP):   # both spins between m and m'
+                fmask |= (1 << x[1]) | (1 << x[2])
+        occ = (orc.basis(ns, n).astype(np.int64) & fmask)[perm]
         starts = np.nonzero(np.r_[True, comp[1:] != comp[:-1]])[0]
         assert len(np.unique(comp)) == len(starts)
         nh = np.diff(o_off)[perm]
         for a, z in zip(starts, np.r_[starts[1:], D]):
-            key = list(zip((-nh[a:z]).tolist(), perm[a:z].tolist()))
+            key = list(zip((-nh[a:z]).tolist(), occ[a:z].tolist(), perm[a:z].tolist()))
             assert key == sorted(key)
         for i in range(D):
             r = perm[i]
