@@ -1056,9 +1056,11 @@ __global__ __launch_bounds__(BS) void k_upt(ApplyArgs<TX, TA> a) {
 // outputs; small windows leave room for many rows).  Threads own four
 // consecutive columns of the window, whose own copy of the down hop table
 // holds window-local targets (no range test per hop).  H_up (x) 1 reads the
-// partner rows of the component from memory (the items of a tile run on one
-// XCD one after another, so those rows' window segments are L2 hits); the
-// four-fermion terms move both spins to other components and read memory.
+// partner rows of the component from memory: with the XCD-partitioned work
+// list the items of a tile run on one XCD one after another, so those rows'
+// window segments are L2 hits; with the shared list (tiles too large for an
+// L2) the whole chip runs one tile at a time and they are Infinity Cache hits.
+// The four-fermion terms move both spins to other components and read memory.
 // UPX = false leaves H_up (x) 1 to a band pass.  Element offsets are 32-bit
 // (D < 2^32).
 // FOLD: the cross term is one table over the fk sites of every w_ud entry
@@ -1323,6 +1325,10 @@ static const Variant kVariants[] = {
     // lean tile kernel, two rows or one row per item, smaller workgroups
     {12, 2, 256, 1024, "gt_r2_w1024"},      {12, 2, 128, 1024, "gt_r2_w1024_b128"},
     {12, 1, 512, 8192, "gt_r1_w8192"},
+    // the whole chip on one tile at a time (shared work list, runs of 20 or
+    // 128 rows per XCD): for tiles larger than an XCD's L2 (N_s = 18: up to
+    // 8000 rows x 32 KB)
+    {12, 1, 512, 8192, "gt_r1_w8192_shared_c20"}, {12, 1, 512, 8192, "gt_r1_w8192_shared_c128"},
 };
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 static constexpr int64_t kDynBudget = 163840 - 8192;  // LDS left for the staged x block
@@ -1476,8 +1482,17 @@ static int64_t max_down_component(const ed_ham_s *h) {
     return m;
 }
 
-// Work list over (up component, window) tiles, XCD-partitioned (items_for).
-static std::vector<int4> tile_items(const std::vector<int32_t> &co, const std::vector<int64_t> &cols, int rows) {
+// Work list over (up component, window) tiles.  chunk = 0: XCD-partitioned
+// (as items_for).  chunk > 0: shared, the tiles in order with runs of `chunk`
+// consecutive items dealt to the eight XCDs in turn, so that the round-robin
+// dispatch spreads each tile over the whole chip, which works on one tile at a
+// time (its slice of x then stays in the Infinity Cache while its rows read
+// their partner rows, when the tile is too large for one XCD's L2), while each
+// run of consecutive rows (whose partners are partly each other) stays on one
+// XCD.
+static std::vector<int4> tile_items(const std::vector<int32_t> &co, const std::vector<int64_t> &cols, int rows,
+                                    int chunk) {
+    constexpr int kX = 8;
     std::vector<int4> L;
     std::vector<double> cost;
     for (size_t A = 0; A + 1 < co.size(); ++A)
@@ -1487,9 +1502,18 @@ static std::vector<int4> tile_items(const std::vector<int32_t> &co, const std::v
                 L.push_back(make_int4((int)u, nr, (int)w, 0));
                 cost.push_back((double)nr * (double)cols[w]);
             }
+    if (chunk > 0) {
+        std::vector<std::vector<int4>> q(kX);
+        for (size_t i = 0; i < L.size(); ++i) q[(i / (size_t)chunk) % kX].push_back(L[i]);
+        size_t len = 1;
+        for (auto &r : q) len = std::max(len, r.size());
+        std::vector<int4> out(len * kX, make_int4(0, 0, 0, 0));
+        for (int x = 0; x < kX; ++x)
+            for (size_t i = 0; i < q[x].size(); ++i) out[x + kX * i] = q[x][i];
+        return out;
+    }
     double total = 0.0;
     for (double c : cost) total += c;
-    constexpr int kX = 8;
     std::vector<std::vector<int4>> run(kX);
     double acc = 0.0;
     for (size_t i = 0; i < L.size(); ++i) {
@@ -1508,8 +1532,8 @@ static std::vector<int4> tile_items(const std::vector<int32_t> &co, const std::v
 // Plan of k_gtile with R rows per tile and windows of about `wtarget` states
 // (consecutive down components merged while they fit; a larger component is a
 // window of its own).  Cached on the handle.
-static const TilePlan *tile_plan(ed_ham_s *h, int R, int64_t wtarget) {
-    const int64_t key = (int64_t)R << 32 | wtarget;
+static const TilePlan *tile_plan(ed_ham_s *h, int R, int64_t wtarget, int chunk) {
+    const int64_t key = (int64_t)chunk << 48 | (int64_t)R << 32 | wtarget;
     for (auto *t : h->tplans)
         if (t->key == key) return t;
     const SpinTab &dn = h->sp[1];
@@ -1575,7 +1599,7 @@ static const TilePlan *tile_plan(ed_ham_s *h, int R, int64_t wtarget) {
     if (ent.empty()) ent.assign(4, 0u);
     std::vector<int64_t> cols;
     for (const int2 &w : win) cols.push_back(w.y);
-    const std::vector<int4> items = tile_items(h->comp_off[0], cols, R);
+    const std::vector<int4> items = tile_items(h->comp_off[0], cols, R, chunk);
     TilePlan *t = new TilePlan();
     try {
         t->key = key;
@@ -1820,10 +1844,10 @@ static void launch_upb(const ApplyArgs<TX, TA> &a, int64_t band, int rw, hipStre
 }
 
 template <typename TX, typename TA, int R, int BS, bool UPX = true>
-static void launch_gtile(ed_ham_s *h, ApplyArgs<TX, TA> a, int64_t wtarget, hipStream_t s) {
+static void launch_gtile(ed_ham_s *h, ApplyArgs<TX, TA> a, int64_t wtarget, hipStream_t s, int chunk = 0) {
     if (h->fk < 0 && !(h->koff == 0 && h->umode <= 1))
         fail(ED_EINVAL, "tile schedule: the cross term is neither a small table nor a uniform on-site U");
-    const TilePlan *t = tile_plan(h, R, wtarget);
+    const TilePlan *t = tile_plan(h, R, wtarget, chunk);
     a.win = t->win.as<int2>();
     a.nwin = t->nwin;
     a.wmax = t->wmax;
@@ -1949,6 +1973,8 @@ static void launch_variant(ed_ham_s *h, const ApplyArgs<TX, TA> &a, int v, hipSt
         case 31: launch_gtile<TX, TA, 2, 256>(h, a, 1024, s); break;
         case 32: launch_gtile<TX, TA, 2, 128>(h, a, 1024, s); break;
         case 33: launch_gtile<TX, TA, 1, 512>(h, a, 8192, s); break;
+        case 34: launch_gtile<TX, TA, 1, 512>(h, a, 8192, s, 20); break;
+        case 35: launch_gtile<TX, TA, 1, 512>(h, a, 8192, s, 128); break;
         default: fail(ED_EINVAL, "bad apply variant %d", v);
     }
 }

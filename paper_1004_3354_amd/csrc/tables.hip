@@ -769,7 +769,7 @@ static void validate(const ed_params *p, int ns) {
 // of hops (descending), then by their occupation of the sites in `fmask` (the
 // sites the four-fermion terms move this spin between), then by rank.
 // Returns the number of components; perm[p] = rank at position p.
-static int component_order(const SpinTab &t, uint32_t fmask, std::vector<int32_t> &perm,
+static int component_order(const SpinTab &t, uint32_t fmask, const char *env, std::vector<int32_t> &perm,
                            std::vector<int32_t> &comp_off) {
     const int64_t dim = t.dim;
     std::vector<int32_t> off((size_t)dim + 1), tgt((size_t)std::max<int64_t>(t.nnz, 1));
@@ -812,9 +812,8 @@ static int component_order(const SpinTab &t, uint32_t fmask, std::vector<int32_t
     // four-fermion sites, so that a four-fermion move, which changes only those
     // sites, maps each run of equal occupation onto a run of the partner
     // component in the same order (its gathers read consecutive addresses);
-    // then by rank.  ED_GROUP_ORDER=hops drops the occupation key,
-    // ED_GROUP_ORDER=rank keeps plain rank order inside a component.
-    const char *env = std::getenv("ED_GROUP_ORDER");
+    // then by rank.  `env` = "hops" drops the occupation key, "rank" keeps
+    // plain rank order inside a component.
     const bool by_rank = env && std::strcmp(env, "rank") == 0;
     if (env && std::strcmp(env, "hops") == 0) fmask = 0u;
     if (!by_rank) {
@@ -839,7 +838,7 @@ static void build_twin(ed_ham_s *h, const ed_params *p, const BasisData &b) {
         uint32_t fmask = 0u;
         for (size_t q = 0; q < h->sp[s].mv_src.size(); ++q)
             fmask |= (1u << h->sp[s].mv_src[q]) | (1u << h->sp[s].mv_dst[q]);
-        nc[s] = component_order(h->sp[s], fmask, perm[s], coff[s]);
+        nc[s] = component_order(h->sp[s], fmask, std::getenv("ED_GROUP_ORDER"), perm[s], coff[s]);
     }
     if (nc[0] < 2 && nc[1] < 2) return;
     ed_ham_s *g = new ed_ham_s();
