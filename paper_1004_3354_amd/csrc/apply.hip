@@ -110,6 +110,7 @@ __global__ __launch_bounds__(BS) void k_apply(ApplyArgs<TX, TA> a) {
     __shared__ int32_t u_src[R][UL];
     __shared__ TA u_amp[R][UL];
     __shared__ int32_t x_src[R][XL], x_tab[R][XL];
+    __shared__ uint32_t x_bits[R][XL];
     __shared__ TA x_amp[R][XL];
     if constexpr (PK) {
         for (int k = threadIdx.x; k < a.namp; k += BS) amps[k] = a.amp_tab[k];
@@ -507,6 +508,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
     __shared__ int32_t u_src[R][UL];
     __shared__ TA u_amp[R][UL];
     __shared__ int32_t x_src[R][XL], x_tab[R][XL];
+    __shared__ uint32_t x_bits[R][XL];
     __shared__ TA x_amp[R][XL];
     __shared__ TA usl[32], xtl[256];
     for (int k = threadIdx.x; k < a.namp; k += BS) amps[k] = a.amp_tab[k];
@@ -562,6 +564,7 @@ __global__ __launch_bounds__(BS) void k_rt(ApplyArgs<TX, TA> a) {
         for (int k = threadIdx.x; k < nxl[r]; k += BS) {
             x_src[r][k] = a.xl_src[xb + k];
             x_tab[r][k] = a.xl_tab[xb + k];
+            x_bits[r][k] = a.dn_mvb[a.xl_tab[xb + k]];
             x_amp[r][k] = a.xl_amp[xb + k];
         }
     }
@@ -1078,6 +1081,7 @@ __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
     __shared__ int32_t u_src[R][UL];
     __shared__ TA u_amp[R][UL];
     __shared__ int32_t x_src[R][XL], x_tab[R][XL];
+    __shared__ uint32_t x_bits[R][XL];
     __shared__ TA x_amp[R][XL];
     __shared__ TA usl[32], xtl[256];
     const int4 it = a.items[blockIdx.x];
@@ -1107,16 +1111,17 @@ __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
         }
         const int32_t hb = a.up_off[u];
         const int n = ok && UPX ? a.up_off[u + 1] - hb : 0;
-        nu[r] = (n + 3) & ~3;
-        for (int k = threadIdx.x; k < nu[r]; k += BS) {
-            u_src[r][k] = k < n ? a.up_tgt[hb + k] : (int32_t)u;
-            u_amp[r][k] = k < n ? a.up_sa[hb + k] : (TA)0;
+        nu[r] = n;
+        for (int k = threadIdx.x; k < n; k += BS) {
+            u_src[r][k] = a.up_tgt[hb + k];
+            u_amp[r][k] = a.up_sa[hb + k];
         }
         const int32_t xb = a.xl_off[u];
         nxl[r] = ok ? a.xl_off[u + 1] - xb : 0;
         for (int k = threadIdx.x; k < nxl[r]; k += BS) {
             x_src[r][k] = a.xl_src[xb + k];
             x_tab[r][k] = a.xl_tab[xb + k];
+            x_bits[r][k] = a.dn_mvb[a.xl_tab[xb + k]];
             x_amp[r][k] = a.xl_amp[xb + k];
         }
     }
@@ -1196,13 +1201,15 @@ __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
                 }
             }
         }
-        // H_up (x) 1: partner rows of the component, four 16-byte loads in flight
+        // H_up (x) 1: partner rows of the component, four 16-byte loads in
+        // flight, then the row's last one to three partners
         if constexpr (UPX) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (r >= nr) break;
-                for (int k = 0; k < nu[r]; k += 4) {
-                    if (full) {
+                if (full) {
+                    int k = 0;
+                    for (; k + 4 <= nu[r]; k += 4) {
                         V v[4];
 #pragma unroll
                         for (int i = 0; i < 4; ++i) v[i] = ld4(a.x + ((uint32_t)u_src[r][k + i] * ddn + c));
@@ -1214,29 +1221,45 @@ __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
                             acc[r][2] += am * (TA)v[i].z;
                             acc[r][3] += am * (TA)v[i].w;
                         }
-                    } else {
+                    }
+                    for (; k < nu[r]; ++k) {
+                        const V v = ld4(a.x + ((uint32_t)u_src[r][k] * ddn + c));
+                        const TA am = u_amp[r][k];
+                        acc[r][0] += am * (TA)v.x;
+                        acc[r][1] += am * (TA)v.y;
+                        acc[r][2] += am * (TA)v.z;
+                        acc[r][3] += am * (TA)v.w;
+                    }
+                } else {
+                    for (int k = 0; k < nu[r]; ++k) {
+                        const TA am = u_amp[r][k];
+                        const TX *row = a.x + (uint32_t)u_src[r][k] * ddn;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const TA am = u_amp[r][k + i];
-                            const TX *row = a.x + (uint32_t)u_src[r][k + i] * ddn;
-#pragma unroll
-                            for (int j = 0; j < 4; ++j)
-                                if (cl + j < wl) acc[r][j] += am * (TA)row[c + j];
-                        }
+                        for (int j = 0; j < 4; ++j)
+                            if (cl + j < wl) acc[r][j] += am * (TA)row[c + j];
                     }
                 }
             }
         }
-        // four-fermion terms: partners in other components, from memory.  The
-        // four gathers of a term are issued unconditionally (a column without a
-        // partner reads the partner row's first element and adds zero), so they
-        // are in flight together instead of one branch and one wait each.
+        // four-fermion terms: partners in other components, from memory.  A
+        // thread none of whose columns has the term's down move (a test on the
+        // column words it already holds) skips the term, table read included;
+        // the others load only their valid columns' partners, all four loads
+        // in flight before the first use.
         if (a.nx) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (r >= nr) break;
 #pragma unroll 2
                 for (int k = 0; k < nxl[r]; ++k) {
+                    const uint32_t mb = x_bits[r][k];
+                    if (mb >> 31) {
+                        const uint32_t sb = mb & 0xFFu, db = (mb >> 8) & 0xFFu;
+                        uint32_t any = 0u;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) any |= (cd[j] >> sb) & ~(cd[j] >> db);
+                        if (!(any & 1u)) continue;
+                    }
                     const TX *src = a.x + (uint32_t)x_src[r][k] * ddn;
                     const TA am = x_amp[r][k];
                     const int32_t *mp = a.dn_mv + (uint32_t)x_tab[r][k] * ddn + c;
@@ -1250,12 +1273,12 @@ __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
                     }
                     TA v[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) v[j] = (TA)src[m[j] >= 0 ? ((uint32_t)m[j] >> 1) : 0u];
-#pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const TA t = (m[j] & 1) ? -am * v[j] : am * v[j];
-                        acc[r][j] += m[j] >= 0 ? t : (TA)0;
+                        v[j] = (TA)0;
+                        if (m[j] >= 0) v[j] = (TA)src[(uint32_t)m[j] >> 1];
                     }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[r][j] += (m[j] & 1) ? -am * v[j] : am * v[j];
                 }
             }
         }
@@ -1657,6 +1680,7 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.dn_st = Dn.states.as<uint32_t>();
     a.dn_c = Dn.cidx.as<uint8_t>();
     a.dn_mv = Dn.mv.as<int32_t>();
+    a.dn_mvb = Dn.mvb.as<uint32_t>();
     a.dn_mvp = Dn.mvp_ok ? Dn.mvp.as<uint32_t>() : nullptr;
     a.umode = h->umode;
     a.umask = h->umask;
@@ -1712,6 +1736,7 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.dn_st = Dn.states.as<uint32_t>();
     a.dn_c = Dn.cidx.as<uint8_t>();
     a.dn_mv = Dn.mv.as<int32_t>();
+    a.dn_mvb = Dn.mvb.as<uint32_t>();
     a.dn_mvp = Dn.mvp_ok ? Dn.mvp.as<uint32_t>() : nullptr;
     a.umode = h->umode;
     a.umask = h->umask;

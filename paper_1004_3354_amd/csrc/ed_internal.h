@@ -160,6 +160,10 @@ struct SpinTab {
     int nmv = 0;              // number of move tables
     DevMem mv;                // int32 [nmv][dim] (target << 1 | sign bit) or -1
     std::vector<int> mv_src, mv_dst;  // move q: electron src -> dst
+    // uint32 [nmv]: bit 31 set when move q's validity is a test on the word the
+    // tile kernel holds per column (the folded cross-term index, or the state
+    // bits without one): source bit (bits 0..7) set, destination bit (8..15) clear
+    DevMem mvb;
     // down spin, when every move shifts the rank by -4..3: all moves of a state
     // in one word, 5 bits per move (valid << 4 | sign << 3 | shift + 4)
     bool mvp_ok = false;
@@ -203,6 +207,7 @@ struct ed_ham_s {
     // every nonzero w_ud entry lies on at most 4 sites: fk sites, per state the
     // bits on them (fcidx) and the 4^fk values
     int fk = -1;                // -1: no folded table
+    std::vector<int> fk_sites;  // bit q of the folded index = occupation of fk_sites[q]
     ed::DevMem fcidx[2];
     ed::DevMem ftab64, ftab32;
     // four-fermion terms
@@ -274,6 +279,7 @@ struct ApplyArgs {
     const uint8_t *dn_c;
     const int32_t *dn_mv;
     const uint32_t *dn_mvp;  // packed down move words, or nullptr
+    const uint32_t *dn_mvb;  // per down move: validity test on the column word (SpinTab::mvb)
     // cross term
     int umode;
     uint32_t umask;

@@ -579,6 +579,7 @@ static void build_cross(ed_ham_s *h, const ed_params *p) {
             }
             ED_HIP(hipDeviceSynchronize());
             h->fk = k;
+            h->fk_sites = fs;
         }
     }
 }
@@ -623,6 +624,25 @@ static void build_xterms(ed_ham_s *h, const ed_params *p) {
                                                           h->grouped ? h->gipos[s].as<int32_t>() : nullptr);
             ED_LAUNCH_CHECK();
         }
+    }
+    // down spin: each move's validity as a test on the column word of the tile
+    // kernel (source occupied, destination empty), so a kernel can skip a term
+    // for columns where the move does not apply before reading its table
+    {
+        SpinTab &t = h->sp[1];
+        std::vector<uint32_t> mb((size_t)std::max(t.nmv, 1), 0u);
+        for (int q = 0; q < t.nmv; ++q) {
+            int sb = t.mv_src[q], db = t.mv_dst[q];
+            if (h->fk >= 0) {
+                sb = db = -1;
+                for (size_t i = 0; i < h->fk_sites.size(); ++i) {
+                    if (h->fk_sites[i] == t.mv_src[q]) sb = (int)i;
+                    if (h->fk_sites[i] == t.mv_dst[q]) db = (int)i;
+                }
+            }
+            if (sb >= 0 && db >= 0 && sb != db) mb[q] = 1u << 31 | (uint32_t)db << 8 | (uint32_t)sb;
+        }
+        upload(t.mvb, mb);
     }
     // down spin: all move tables packed into one word per state when every move
     // shifts the rank by -4..3 (moves on the lowest sites): 5 bits per move,
