@@ -1069,7 +1069,7 @@ __global__ __launch_bounds__(BS) void k_upt(ApplyArgs<TX, TA> a) {
 // FOLD: the cross term is one table over the fk sites of every w_ud entry
 // (diagonal = e_up + e_dn + T[(c_up << fk) | c_dn]); otherwise it is a uniform
 // on-site U, U0 popc(s_up & s_dn & umask), and nothing else.
-template <typename TX, typename TA, int R, int BS, bool UPX, bool FOLD>
+template <typename TX, typename TA, int R, int BS, bool UPX, bool FOLD, bool H16>
 __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
     using RVt = typename RV<TX, R>::t;
     using V = typename V4<TX>::t;
@@ -1158,15 +1158,23 @@ __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
     for (int cl = 4 * (int)threadIdx.x; cl < wl; cl += 4 * BS) {
         const bool full = cl + 4 <= wl;
         const uint32_t c = w0 + (uint32_t)cl;
-        // the column data first (the diagonal depends on it)
+        // the column data first (the diagonal depends on it), one 16-byte load
+        // per array for the four columns
         TA edn[4];
         uint32_t cd[4];
+        if (full) {
+            const typename V4<TA>::t e4 = ld4(a.dn_e + c);
+            const typename V4<uint32_t>::t c4 = ld4(FOLD ? a.dn_fc32 + c : a.dn_st + c);
+            edn[0] = e4.x; edn[1] = e4.y; edn[2] = e4.z; edn[3] = e4.w;
+            cd[0] = c4.x; cd[1] = c4.y; cd[2] = c4.z; cd[3] = c4.w;
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t q = c + (uint32_t)min(j, wl - 1 - cl);  // ragged end: repeat the last column
-            edn[j] = (TA)a.dn_e[q];
-            if constexpr (FOLD) cd[j] = a.dn_fc[q];
-            else cd[j] = a.dn_st[q];
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t q = c + (uint32_t)min(j, wl - 1 - cl);  // ragged end: repeat the last column
+                edn[j] = (TA)a.dn_e[q];
+                if constexpr (FOLD) cd[j] = a.dn_fc32[q];
+                else cd[j] = a.dn_st[q];
+            }
         }
         TA acc[R][4];
 #pragma unroll
@@ -1188,16 +1196,34 @@ __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
             const int32_t eb = a.wsl_off[gs];
             const int32_t kk = (a.wsl_off[gs + 1] - eb) >> 6;
             const uint4 *ep = a.wel4 + eb + lane;
+            if constexpr (H16) {
+                // 16-bit entries: one 16-byte load gives two hops of the four columns
+                for (int32_t k = 0; k < kk; ++k) {
+                    const uint4 e = ep[k * 64];
+                    const uint32_t ew[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+                    for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t h = (ew[2 * hk + (j >> 1)] >> (16 * (j & 1))) & 0xFFFFu;
+                            const TA am = amps[h >> 10];
+                            const RVt v = *reinterpret_cast<const RVt *>(xs + (h & 0x3FFu) * R);
+#pragma unroll
+                            for (int r = 0; r < R; ++r) acc[r][j] += am * (TA)rv_get<TX, R>(v, r);
+                        }
+                }
+            } else {
 #pragma unroll 2
-            for (int32_t k = 0; k < kk; ++k) {
-                const uint4 e = ep[k * 64];
-                const uint32_t ev[4] = {e.x, e.y, e.z, e.w};
+                for (int32_t k = 0; k < kk; ++k) {
+                    const uint4 e = ep[k * 64];
+                    const uint32_t ev[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const TA am = amps[ev[j] >> 20];
-                    const RVt v = *reinterpret_cast<const RVt *>(xs + (ev[j] & 0xFFFFFu) * R);
+                    for (int j = 0; j < 4; ++j) {
+                        const TA am = amps[ev[j] >> 20];
+                        const RVt v = *reinterpret_cast<const RVt *>(xs + (ev[j] & 0xFFFFFu) * R);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) acc[r][j] += am * (TA)rv_get<TX, R>(v, r);
+                        for (int r = 0; r < R; ++r) acc[r][j] += am * (TA)rv_get<TX, R>(v, r);
+                    }
                 }
             }
         }
@@ -1299,9 +1325,9 @@ __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
     }
 }
 
-template <typename TX, typename TA, int R, int BS, bool UPX, bool FOLD>
+template <typename TX, typename TA, int R, int BS, bool UPX, bool FOLD, bool H16>
 __global__ __launch_bounds__(BS) void k_gtile(ApplyArgs<TX, TA> a) {
-    gtile_body<TX, TA, R, BS, UPX, FOLD>(a);
+    gtile_body<TX, TA, R, BS, UPX, FOLD, H16>(a);
 }
 
 // ---------------------------------------------------------- variant table --
@@ -1592,29 +1618,42 @@ static const TilePlan *tile_plan(ed_ham_s *h, int R, int64_t wtarget, int chunk)
             idx.emplace(sa[e], (int)vals.size());
             vals.push_back(sa[e]);
         }
-    // per-window slices of 256 states, lane l holding states 4l..4l+3
+    // per-window slices of 256 states, lane l holding states 4l..4l+3; entry
+    // (hop k, state q) = window-local target | amplitude index (padding: the
+    // state itself with amplitude index 0)
+    int wmax = 0;
+    for (const int2 &w : win) wmax = std::max(wmax, w.y);
+    const bool half = wmax <= 1024 && vals.size() <= 64;
+    auto entry = [&](const int2 &w, int64_t q, int k) -> uint32_t {
+        uint32_t v = q < w.x + w.y ? (uint32_t)(q - w.x) : 0u;
+        if (q < w.x + w.y && k < off[q + 1] - off[q]) {
+            const int64_t e = off[q] + k, t = (int64_t)tgt[e] - w.x;
+            if (t < 0 || t >= w.y) fail(ED_EDEVICE, "tile plan: a down hop leaves its component");
+            v = (uint32_t)t | ((uint32_t)idx.at(sa[e]) << (half ? 10 : 20));
+        }
+        return v;
+    };
     std::vector<int32_t> first, soff;
     std::vector<uint32_t> ent;
-    int wmax = 0;
     for (const int2 &w : win) {
-        wmax = std::max(wmax, w.y);
         first.push_back((int32_t)soff.size());
         for (int64_t s0 = 0; s0 < w.y; s0 += 256) {
             int kk = 0;
             for (int64_t q = w.x + s0; q < std::min<int64_t>(w.x + w.y, w.x + s0 + 256); ++q)
                 kk = std::max(kk, off[q + 1] - off[q]);
             soff.push_back((int32_t)(ent.size() / 4));
-            for (int k = 0; k < kk; ++k)
-                for (int l = 0; l < 256; ++l) {
-                    const int64_t q = w.x + s0 + l;
-                    uint32_t v = q < w.x + w.y ? (uint32_t)(q - w.x) : 0u;
-                    if (q < w.x + w.y && k < off[q + 1] - off[q]) {
-                        const int64_t e = off[q] + k, t = (int64_t)tgt[e] - w.x;
-                        if (t < 0 || t >= w.y) fail(ED_EDEVICE, "tile plan: a down hop leaves its component");
-                        v = (uint32_t)t | ((uint32_t)idx.at(sa[e]) << 20);
-                    }
-                    ent.push_back(v);
-                }
+            if (half) {
+                for (int k = 0; k < kk; k += 2)
+                    for (int l = 0; l < 64; ++l)
+                        for (int hk = 0; hk < 2; ++hk)
+                            for (int j = 0; j < 4; j += 2) {
+                                const int64_t q = w.x + s0 + 4 * l + j;
+                                ent.push_back(entry(w, q, k + hk) | entry(w, q + 1, k + hk) << 16);
+                            }
+            } else {
+                for (int k = 0; k < kk; ++k)
+                    for (int l = 0; l < 256; ++l) ent.push_back(entry(w, w.x + s0 + l, k));
+            }
         }
     }
     first.push_back((int32_t)soff.size());
@@ -1629,6 +1668,7 @@ static const TilePlan *tile_plan(ed_ham_s *h, int R, int64_t wtarget, int chunk)
         t->nwin = (int)win.size();
         t->wmax = wmax;
         t->namp = (int)vals.size();
+        t->half = half ? 1 : 0;
         t->nitems = (int64_t)items.size();
         upload(t->win, win);
         upload(t->wsl_first, first);
@@ -1701,6 +1741,7 @@ ApplyArgs<double, double> make_args<double, double>(const ed_ham_s *h, const voi
     a.ftab = h->ftab64.as<double>();
     a.up_fc = h->fcidx[0].as<uint8_t>();
     a.dn_fc = h->fcidx[1].as<uint8_t>();
+    a.dn_fc32 = h->dn_fc32.as<uint32_t>();
     return a;
 }
 
@@ -1757,6 +1798,7 @@ ApplyArgs<float, float> make_args<float, float>(const ed_ham_s *h, const void *x
     a.ftab = h->ftab32.as<float>();
     a.up_fc = h->fcidx[0].as<uint8_t>();
     a.dn_fc = h->fcidx[1].as<uint8_t>();
+    a.dn_fc32 = h->dn_fc32.as<uint32_t>();
     return a;
 }
 
@@ -1883,15 +1925,10 @@ static void launch_gtile(ed_ham_s *h, ApplyArgs<TX, TA> a, int64_t wtarget, hipS
     a.namp = t->namp;
     a.amp_tab = sizeof(TA) == 8 ? (const TA *)t->amp64.p : (const TA *)t->amp32.p;
     const size_t shm = (((size_t)R * (size_t)t->wmax * sizeof(TX) + 15) & ~(size_t)15) + (size_t)t->namp * sizeof(TA);
-    if (h->fk >= 0) {
-        auto kern = k_gtile<TX, TA, R, BS, UPX, true>;
-        allow_lds(kern);
-        kern<<<(unsigned)t->nitems, BS, shm, s>>>(a);
-    } else {
-        auto kern = k_gtile<TX, TA, R, BS, UPX, false>;
-        allow_lds(kern);
-        kern<<<(unsigned)t->nitems, BS, shm, s>>>(a);
-    }
+    auto kern = h->fk >= 0 ? (t->half ? k_gtile<TX, TA, R, BS, UPX, true, true> : k_gtile<TX, TA, R, BS, UPX, true, false>)
+                           : (t->half ? k_gtile<TX, TA, R, BS, UPX, false, true> : k_gtile<TX, TA, R, BS, UPX, false, false>);
+    allow_lds(kern);
+    kern<<<(unsigned)t->nitems, BS, shm, s>>>(a);
     ED_LAUNCH_CHECK();
 }
 

@@ -120,12 +120,16 @@ namespace ed {
 struct TilePlan {
     int64_t key = 0;
     int nwin = 0, wmax = 0, namp = 0;
+    int half = 0;      // 1: 16-bit entries (windows of at most 1024 states, at most 64 amplitudes)
     int64_t nitems = 0;
     DevMem win;        // int2 [nwin]: (first position, length)
     DevMem wsl_first;  // int32 [nwin + 1]: first slice of each window
     DevMem wsl_off;    // int32 [nslices + 1]: slice offsets in uint4 units
     DevMem wel4;       // uint4 [(slice, k, lane)]: four consecutive states per lane,
-                       // window-local target (bits 0..19) | amplitude index (20..31)
+                       // window-local target (bits 0..19) | amplitude index (20..31);
+                       // half: uint4 [(slice, pair of hops k, lane)], 16-bit entries
+                       // target (bits 0..9) | amplitude index (10..15), words
+                       // (hop 2k: states 0|1, 2|3; hop 2k+1: states 0|1, 2|3)
     DevMem amp64, amp32;
     DevMem items;      // int4 [nitems]
 };
@@ -209,6 +213,7 @@ struct ed_ham_s {
     int fk = -1;                // -1: no folded table
     std::vector<int> fk_sites;  // bit q of the folded index = occupation of fk_sites[q]
     ed::DevMem fcidx[2];
+    ed::DevMem dn_fc32;         // uint32 [ddn]: fcidx[1] widened, four columns per 16-byte load
     ed::DevMem ftab64, ftab32;
     // four-fermion terms
     int nx = 0;
@@ -309,6 +314,7 @@ struct ApplyArgs {
     int fk;
     const TA *ftab;
     const uint8_t *up_fc, *dn_fc;
+    const uint32_t *dn_fc32;
 };
 
 // Build all tables of a Hamiltonian handle (tables.hip).

@@ -578,6 +578,9 @@ static void build_cross(ed_ham_s *h, const ed_params *p) {
                 ED_LAUNCH_CHECK();
             }
             ED_HIP(hipDeviceSynchronize());
+            std::vector<uint8_t> f8((size_t)h->sp[1].dim);
+            if (!f8.empty()) ED_HIP(hipMemcpy(f8.data(), h->fcidx[1].p, f8.size(), hipMemcpyDeviceToHost));
+            upload(h->dn_fc32, f8.empty() ? std::vector<uint32_t>(1, 0u) : std::vector<uint32_t>(f8.begin(), f8.end()));
             h->fk = k;
             h->fk_sites = fs;
         }
