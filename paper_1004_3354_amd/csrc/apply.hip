@@ -1230,11 +1230,40 @@ __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
         // H_up (x) 1: partner rows of the component, four 16-byte loads in
         // flight, then the row's last one to three partners
         if constexpr (UPX) {
+            // several rows: their first partners in common groups of four, so
+            // that 4 R loads are in flight together
+            int kc = 0;
+            if constexpr (R > 1) {
+                if (full) {
+                    kc = nu[0];
+#pragma unroll
+                    for (int r = 1; r < R; ++r) kc = r < nr ? min(kc, nu[r]) : kc;
+                    kc &= ~3;
+                    for (int k = 0; k < kc; k += 4) {
+                        V v[R][4];
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                v[r][i] = ld4(a.x + ((uint32_t)u_src[r < nr ? r : 0][k + i] * ddn + c));
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const TA am = r < nr ? u_amp[r][k + i] : (TA)0;
+                                acc[r][0] += am * (TA)v[r][i].x;
+                                acc[r][1] += am * (TA)v[r][i].y;
+                                acc[r][2] += am * (TA)v[r][i].z;
+                                acc[r][3] += am * (TA)v[r][i].w;
+                            }
+                    }
+                }
+            }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (r >= nr) break;
                 if (full) {
-                    int k = 0;
+                    int k = kc;
                     for (; k + 4 <= nu[r]; k += 4) {
                         V v[4];
 #pragma unroll
