@@ -1299,41 +1299,61 @@ __device__ __forceinline__ void gtile_body(const ApplyArgs<TX, TA> &a) {
         // four-fermion terms: partners in other components, from memory.  A
         // thread none of whose columns has the term's down move (a test on the
         // column words it already holds) skips the term, table read included;
-        // the others load only their valid columns' partners, all four loads
-        // in flight before the first use.
+        // the others load only their valid columns' partners.  The rows' k-th
+        // terms go together, so their table reads and then their partner
+        // loads are in flight at once.
         if (a.nx) {
+            int kx = 0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (r >= nr) break;
+            for (int r = 0; r < R; ++r) kx = r < nr ? max(kx, nxl[r]) : kx;
 #pragma unroll 2
-                for (int k = 0; k < nxl[r]; ++k) {
-                    const uint32_t mb = x_bits[r][k];
-                    if (mb >> 31) {
-                        const uint32_t sb = mb & 0xFFu, db = (mb >> 8) & 0xFFu;
-                        uint32_t any = 0u;
+            for (int k = 0; k < kx; ++k) {
+                bool go[R];
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) any |= (cd[j] >> sb) & ~(cd[j] >> db);
-                        if (!(any & 1u)) continue;
-                    }
-                    const TX *src = a.x + (uint32_t)x_src[r][k] * ddn;
-                    const TA am = x_amp[r][k];
-                    const int32_t *mp = a.dn_mv + (uint32_t)x_tab[r][k] * ddn + c;
-                    int32_t m[4];
-                    if (full) {
-                        const int4 t4 = *reinterpret_cast<const int4 *>(mp);
-                        m[0] = t4.x; m[1] = t4.y; m[2] = t4.z; m[3] = t4.w;
-                    } else {
+                for (int r = 0; r < R; ++r) {
+                    go[r] = r < nr && k < nxl[r];
+                    if (go[r]) {
+                        const uint32_t mb = x_bits[r][k];
+                        if (mb >> 31) {
+                            const uint32_t sb = mb & 0xFFu, db = (mb >> 8) & 0xFFu;
+                            uint32_t any = 0u;
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) m[j] = cl + j < wl ? mp[j] : -1;
+                            for (int j = 0; j < 4; ++j) any |= (cd[j] >> sb) & ~(cd[j] >> db);
+                            go[r] = (any & 1u) != 0u;
+                        }
                     }
-                    TA v[4];
+                }
+                int32_t m[R][4];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) m[r][j] = -1;
+                    if (go[r]) {
+                        const int32_t *mp = a.dn_mv + (uint32_t)x_tab[r][k] * ddn + c;
+                        if (full) {
+                            const int4 t4 = *reinterpret_cast<const int4 *>(mp);
+                            m[r][0] = t4.x; m[r][1] = t4.y; m[r][2] = t4.z; m[r][3] = t4.w;
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) m[r][j] = cl + j < wl ? mp[j] : -1;
+                        }
+                    }
+                }
+                TA v[R][4];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const TX *src = a.x + (uint32_t)x_src[r][go[r] ? k : 0] * ddn;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        v[j] = (TA)0;
-                        if (m[j] >= 0) v[j] = (TA)src[(uint32_t)m[j] >> 1];
+                        v[r][j] = (TA)0;
+                        if (m[r][j] >= 0) v[r][j] = (TA)src[(uint32_t)m[r][j] >> 1];
                     }
+                }
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[r][j] += (m[j] & 1) ? -am * v[j] : am * v[j];
+                for (int r = 0; r < R; ++r) {
+                    const TA am = go[r] ? x_amp[r][k] : (TA)0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[r][j] += (m[r][j] & 1) ? -am * v[r][j] : am * v[r][j];
                 }
             }
         }
