@@ -24,6 +24,7 @@
 #include <map>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "ed_internal.h"
@@ -1672,7 +1673,9 @@ static const TilePlan *tile_plan(ed_ham_s *h, int R, int64_t wtarget, int chunk)
     // state itself with amplitude index 0)
     int wmax = 0;
     for (const int2 &w : win) wmax = std::max(wmax, w.y);
-    const bool half = wmax <= 1024 && vals.size() <= 64;
+    // ED_TILE_ENTRY_BITS=32 keeps 32-bit entries for small windows too
+    const char *bits = std::getenv("ED_TILE_ENTRY_BITS");
+    const bool half = wmax <= 1024 && vals.size() <= 64 && !(bits && std::strcmp(bits, "32") == 0);
     auto entry = [&](const int2 &w, int64_t q, int k) -> uint32_t {
         uint32_t v = q < w.x + w.y ? (uint32_t)(q - w.x) : 0u;
         if (q < w.x + w.y && k < off[q + 1] - off[q]) {

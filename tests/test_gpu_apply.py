@@ -242,6 +242,19 @@ GROUPED = [c for c in SMALL + EDGE if c[0].startswith("kan")]
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("name,phys,sec_nn", GROUPED, ids=[c[0] for c in GROUPED])
 def test_grouped_apply_parity_all_schedules(name, phys, sec_nn, prec):
+    _grouped_parity(phys, sec_nn, prec, name)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("name,phys,sec_nn", GROUPED[:3], ids=[c[0] for c in GROUPED[:3]])
+def test_grouped_apply_parity_wide_entries(name, phys, sec_nn, prec, monkeypatch):
+    """The tile kernel's 32-bit hop entries (the form the N_s = 18 windows
+    need) on the small sectors, which otherwise take the 16-bit form."""
+    monkeypatch.setenv("ED_TILE_ENTRY_BITS", "32")
+    _grouped_parity(phys, sec_nn, prec, name, prefix="gt_")
+
+
+def _grouped_parity(phys, sec_nn, prec, name, prefix=None):
     ed = gpu_ed()
     nup, ndn = sec_nn
     b, H = build(phys, nup, ndn, prec)
@@ -267,7 +280,7 @@ def test_grouped_apply_parity_all_schedules(name, phys, sec_nn, prec):
     H.to_grouped(xd, xg)
     checked = 0
     for v in range(ed.variant_count()):
-        if not G.variant_fits(v):
+        if not G.variant_fits(v) or (prefix and not ed.variant_name(v).startswith(prefix)):
             continue
         yg = torch.full_like(xd, float("nan"))
         G.apply_variant(v, xg, yg)
