@@ -656,9 +656,12 @@ def main():
     e0_18 = None
     if not args.no_e0_ns18 and not args.no_e0 and not args.no_ns18:
         try:
-            # FP32-mixed: E0, then the 3 lowest levels (20 stored vectors keeping 10);
-            # FP64: E0 (11 stored 18.9 GB vectors keeping 5)
-            e0_18 = lowest_leg(4, [ed.ED_FP32], 3, dict(tol=1e-7, reorth=3, keep=10, max_basis=20, max_iter=3000), 4)
+            # FP32-mixed: E0 (16 stored vectors keeping 8, the fastest of 11..20 for
+            # E0), then the 3 lowest levels (20 keeping 10); FP64: E0 (11 stored
+            # 18.9 GB vectors keeping 5)
+            e0_18 = lowest_leg(4, [ed.ED_FP32], 1, dict(tol=1e-7, reorth=3, keep=8, max_basis=16, max_iter=3000), 4)
+            low3 = lowest_leg(4, [ed.ED_FP32], 3, dict(tol=1e-7, reorth=3, keep=10, max_basis=20, max_iter=3000), 4)
+            e0_18["fp32_mixed_3_lowest"] = low3["fp32_mixed"]
             e0_18.update(lowest_leg(4, [ed.ED_FP64], 1, dict(tol=1e-7, reorth=3, keep=5, max_basis=11, max_iter=3000),
                                     4))
             a, c = e0_18["fp64"], e0_18["fp32_mixed"]
